@@ -1,0 +1,223 @@
+"""Benchmark of the TNLM hot path on one MI355X.
+
+One step = one pass of the whole hot path over the clinical-size
+enhancement workload (10 phases of 256x256x128 voxels, patch 3^3, window
+7^3, h = 0.04, mu = 0.5):
+  * 20 Gauss-Jacobi steps (Eq. (8)), weight source u <- f every 5 steps,
+  * log-normalisers of the final iterate (weights, Eq. (3)),
+  * the TNLM energy forward with its per-voxel statistics,
+  * the Eq. (6) operator,
+  * the exact adjoint (dE/df + dE/du of E(f; f)) from the saved statistics.
+`value` counts the 20 Jacobi sweeps as voxel-updates (20 * 10*256*256*128)
+and divides by the wall time of the whole step, so the energy and gradient
+passes count against it. Inputs are resident on the GPU before timing.
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("TNLM voxel-updates/s + fwd/adjoint ms, 10×256²×128, "
+          "FP32 vs BF16, % VALU peak")
+# MI355X FP32 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2 (packed)
+# x 2.4 GHz
+PEAK_FP32_TFLOPS = 157.3
+# algorithmic flops per Jacobi voxel-update and search offset, patch 3^3:
+# squared difference 2 + separable 3-tap box sums 6 (once per link), then per
+# direction: exponent 2, numerator FMA 2, normaliser add 1 (x2 directions)
+FLOP_PER_UPDATE_PER_OFFSET = 18
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(w, target_s):
+    """Time the FP64 oracle on a bounded sample of the same workload: one
+    Jacobi step (u = f = g) at a random sample of voxels."""
+    import numpy as np
+
+    from oracle import oracle
+    from phantom import workload_inputs
+    g64 = workload_inputs(w, out_dtype=np.float32)[0].astype(np.float64)
+    rng = np.random.default_rng(7)
+    total = g64.size
+    n = 256
+    idx = rng.choice(total, size=n, replace=False)
+    t0 = time.perf_counter()
+    oracle.jacobi(g64, g64, g64, w.mu, w.d, w.M, w.h, idx=idx)
+    dt = time.perf_counter() - t0
+    n2 = int(max(256, min(total, n * max(1.0, target_s / max(dt, 1e-3)))))
+    idx = rng.choice(total, size=n2, replace=False)
+    t0 = time.perf_counter()
+    oracle.jacobi(g64, g64, g64, w.mu, w.d, w.M, w.h, idx=idx)
+    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": n2 / dt, "unit": "voxel-updates/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"one Gauss-Jacobi step of the 10x256x256x128 "
+                      f"workload (u=f=g) at {n2} random voxels, FP64, "
+                      f"{dt:.1f} s on {threads} OpenMP threads"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="enh256")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-dtypes", action="store_true",
+                    help="skip the BF16/FP16 storage comparison")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: the TNLM path here is a "
+              "single-GPU build (no multi-GPU sharding); use --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1201_2450_amd as tnlm
+    from phantom import WORKLOADS, workload_inputs
+
+    w = WORKLOADS[args.workload]
+    dev = torch.device("cuda", 0)
+    log(f"generating {w.name} {w.shape} ...")
+    g_host = workload_inputs(w, out_dtype=np.float32)[0]
+    g = torch.from_numpy(g_host).to(dev)
+    del g_host
+    d, M, h, mu = w.d, w.M, w.h, w.mu
+    nvox = w.nvox
+    W = (2 * M + 1) ** 3
+    iters, every = w.iters, w.recompute_every or 1
+
+    f_a = torch.empty_like(g)
+    f_b = torch.empty_like(g)
+    u_snap = torch.empty_like(g)
+
+    EV = lambda: torch.cuda.Event(enable_timing=True)
+    names = ["jacobi", "weights_lse", "energy_fwd", "grad_eq6", "adjoint"]
+
+    def step(timing):
+        ev = {k: [] for k in names}
+        f, nxt = f_a, f_b
+        f.copy_(g)
+        for k in range(iters):
+            if k % every == 0:
+                u_snap.copy_(f)
+            e0, e1 = EV(), EV()
+            e0.record()
+            tnlm.jacobi_step(u_snap, f, g, mu, d=d, M=M, h=h, out=nxt)
+            e1.record()
+            ev["jacobi"].append((e0, e1))
+            f, nxt = nxt, f
+
+        def timed(name, fn):
+            e0, e1 = EV(), EV()
+            e0.record()
+            r = fn()
+            e1.record()
+            ev[name].append((e0, e1))
+            return r
+
+        timed("weights_lse", lambda: tnlm.weights(f, d=d, M=M, h=h))
+        e, est = timed("energy_fwd",
+                       lambda: tnlm.energy(f, d=d, M=M, h=h, want_stats=True))
+        timed("grad_eq6", lambda: tnlm.grad(f, d=d, M=M, h=h, mode="eq6"))
+        timed("adjoint", lambda: tnlm.grad(f, d=d, M=M, h=h, mode="exact",
+                                           stats=est, total=True))
+        return ev, e
+
+    log(f"warmup x{args.warmup} ...")
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    log(f"timing x{args.steps} ...")
+    all_ev = {k: [] for k in names}
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        ev, e = step(True)
+        for k in names:
+            all_ev[k].extend(ev[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = 1e3 * wall / args.steps
+    ms = {k: float(np.mean([a.elapsed_time(b) for a, b in all_ev[k]]))
+          for k in names}
+    E = float(e[0]) + float(e[1])
+    value = iters * nvox / (ms_step / 1e3)
+    log(f"step {ms_step:.2f} ms; per-op ms {ms}; E = {E}")
+
+    # dominant kernel: the Gauss-Jacobi step
+    alg_flop = FLOP_PER_UPDATE_PER_OFFSET * W * nvox
+    achieved = alg_flop / (ms["jacobi"] / 1e3) / 1e12
+    roofline = {"bound": "alu", "achieved": achieved,
+                "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                "kernel": "tnlm_jacobi_step",
+                "algorithmic_flop_per_launch": alg_flop}
+
+    dtypes = {}
+    if not args.no_dtypes:
+        for name, dt in (("bf16", torch.bfloat16), ("f16", torch.float16)):
+            gq = g.to(dt)
+            outq = torch.empty_like(gq)
+            tnlm.jacobi_step(gq, gq, gq, mu, d=d, M=M, h=h, out=outq)
+            torch.cuda.synchronize()
+            reps = 3
+            e0, e1 = EV(), EV()
+            e0.record()
+            for _ in range(reps):
+                tnlm.jacobi_step(gq, gq, gq, mu, d=d, M=M, h=h, out=outq)
+            e1.record()
+            torch.cuda.synchronize()
+            jms = e0.elapsed_time(e1) / reps
+            dtypes[name] = {"jacobi_ms": jms,
+                            "jacobi_voxel_updates_per_s": nvox / (jms / 1e3)}
+            del gq, outq
+        dtypes["f32"] = {"jacobi_ms": ms["jacobi"],
+                         "jacobi_voxel_updates_per_s":
+                             nvox / (ms["jacobi"] / 1e3)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the FP64 oracle on a sample ...")
+        cpu = cpu_baseline(w, args.cpu_seconds)
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "voxel-updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": w.name, "phases": w.np_,
+                   "grid": [w.nx, w.ny, w.nz], "patch": 2 * d + 1,
+                   "window": 2 * M + 1, "h": h, "mu": mu,
+                   "jacobi_steps": iters, "weights_every": every,
+                   "step": "20 Jacobi + lse + energy fwd + Eq.6 + adjoint"},
+        "breakdown_ms": ms,
+        "energy": E,
+        "jacobi_voxel_updates_per_s": nvox / (ms["jacobi"] / 1e3),
+        "storage_dtypes": dtypes,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "paper_context": {"tnlm_e_per_iteration_s": 55.07,
+                          "hardware": "NVIDIA Tesla C1060",
+                          "workload": "10 x 128^3, window and patch unstated",
+                          "derived_voxel_updates_per_s": 3.8e5},
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

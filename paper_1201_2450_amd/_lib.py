@@ -1,0 +1,81 @@
+"""ctypes loader for libtnlm.so (the HIP library built from csrc/).
+
+Argument marshalling only. If the library has not been built this module
+raises at import time: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtnlm.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "tnlm.h")
+
+# values of the enums in include/tnlm.h
+F32, BF16, F16 = 0, 1, 2
+GRAD_EQ6, GRAD_EXACT = 0, 1
+OP_WEIGHTS, OP_JACOBI, OP_ENERGY, OP_GRAD_EQ6, OP_GRAD_EXACT = 0, 1, 2, 3, 4
+OK, EINVAL, ENULL, EALIAS, ERANGE, EWORKSPACE, EHIP = 0, -1, -2, -3, -4, -5, -6
+
+
+class Geom(ctypes.Structure):
+    """struct tnlm_geom."""
+    _fields_ = [("np", ctypes.c_int32), ("nx", ctypes.c_int32),
+                ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("patch_r", ctypes.c_int32), ("search_r", ctypes.c_int32),
+                ("h", ctypes.c_float)]
+
+
+class TNLMError(RuntimeError):
+    def __init__(self, code, what):
+        self.code = code
+        super().__init__(f"{what}: tnlm status {code} "
+                         f"({strerror(code)})")
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"libtnlm.so not found at {LIB_PATH}: build it first with "
+            "`python -m paper_1201_2450_amd.build` (there is no CPU fallback)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, fp = ctypes.c_void_p, ctypes.c_void_p
+    gp = ctypes.POINTER(Geom)
+    i, sz = ctypes.c_int, ctypes.c_size_t
+    lib.tnlm_weights.argtypes = [gp, i, vp, fp, fp, vp]
+    lib.tnlm_jacobi_step.argtypes = [gp, i, vp, vp, vp, ctypes.c_float, vp,
+                                     vp]
+    lib.tnlm_energy.argtypes = [gp, i, vp, vp, fp, fp, vp, sz, vp]
+    lib.tnlm_grad.argtypes = [gp, i, vp, vp, i, fp, fp, fp, vp, sz, vp]
+    lib.tnlm_workspace_bytes.argtypes = [gp, i]
+    lib.tnlm_workspace_bytes.restype = sz
+    lib.tnlm_strerror.argtypes = [i]
+    lib.tnlm_strerror.restype = ctypes.c_char_p
+    lib.tnlm_version.argtypes = []
+    lib.tnlm_version.restype = ctypes.c_char_p
+    for name in ("tnlm_weights", "tnlm_jacobi_step", "tnlm_energy",
+                 "tnlm_grad"):
+        getattr(lib, name).restype = ctypes.c_int
+    return lib
+
+
+lib = _load()
+
+
+def strerror(code: int) -> str:
+    return lib.tnlm_strerror(int(code)).decode()
+
+
+def check(code: int, what: str):
+    if code != OK:
+        raise TNLMError(code, what)
+
+
+def header_functions():
+    """Names of the functions include/tnlm.h declares."""
+    with open(HEADER) as fh:
+        text = fh.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tnlm_[a-z_0-9]+)\s*\(", text)))

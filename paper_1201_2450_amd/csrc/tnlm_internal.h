@@ -1,0 +1,97 @@
+// Internal declarations shared by the HIP translation units of libtnlm.
+// Not part of the public ABI (include/tnlm.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/tnlm.h"
+
+namespace tnlm {
+
+// Derived geometry passed by value to every kernel.
+struct Geo {
+    int np, nx, ny, nz;  // phases and grid, z fastest
+    int d, M;            // patch radius, search radius
+    int S;               // 2M+1
+    int W;               // (2M+1)^3 offsets
+    int64_t N;           // voxels per phase
+    float inv2h2;        // 1/(2h^2): exponent of Eq. (3) is -D * inv2h2
+    float c2;            // log2(e)/(2h^2): same exponent in base-2 units
+};
+
+// ---- storage types ---------------------------------------------------------
+// u, f, g and f_out are stored as float, bfloat16 (raw uint16 bits) or
+// float16; arithmetic is always float.
+struct bf16_t {
+    uint16_t bits;
+};
+
+__device__ __forceinline__ float load_f(const float *p, int64_t i) { return p[i]; }
+__device__ __forceinline__ float load_f(const bf16_t *p, int64_t i)
+{
+    return __uint_as_float(((uint32_t)p[i].bits) << 16);
+}
+__device__ __forceinline__ float load_f(const _Float16 *p, int64_t i) { return (float)p[i]; }
+
+__device__ __forceinline__ void store_f(float *p, int64_t i, float v) { p[i] = v; }
+__device__ __forceinline__ void store_f(bf16_t *p, int64_t i, float v)
+{
+    // round to nearest even; quiet NaN stays NaN
+    uint32_t x = __float_as_uint(v);
+    uint16_t r;
+    if ((x & 0x7fffffffu) > 0x7f800000u)
+        r = (uint16_t)((x >> 16) | 0x0040u);
+    else
+        r = (uint16_t)((x + 0x7fffu + ((x >> 16) & 1u)) >> 16);
+    p[i].bits = r;
+}
+__device__ __forceinline__ void store_f(_Float16 *p, int64_t i, float v) { p[i] = (_Float16)v; }
+
+// ---- compensated (double-float) accumulation for the energy ---------------
+struct dfloat {
+    float hi, lo;
+};
+
+// Knuth's TwoSum of the high parts, low parts added, then renormalised.
+__device__ __forceinline__ dfloat df_add(dfloat a, dfloat b)
+{
+    float s = a.hi + b.hi;
+    float bb = s - a.hi;
+    float err = (a.hi - (s - bb)) + (b.hi - bb);
+    float lo = err + a.lo + b.lo;
+    float hi = s + lo;
+    lo = lo - (hi - s);
+    return dfloat{hi, lo};
+}
+
+// ---- kernel launchers (defined in the .hip files) --------------------------
+enum FwdMode { FWD_WEIGHTS = 0, FWD_JACOBI = 1, FWD_EQ6 = 2, FWD_ENERGY = 3 };
+
+struct FwdArgs {
+    const void *u, *f, *g;
+    float mu;
+    void *out;       // JACOBI: storage dtype volume; EQ6: float volume
+    float *w;        // WEIGHTS: [np][2][W][N] or null
+    float *lse;      // WEIGHTS: [np][2][N] or null
+    float *stats;    // ENERGY: [np][2][2][N] or null
+    dfloat *partial; // ENERGY: per-block partial sums
+};
+
+struct GradArgs {
+    const void *u, *f;
+    const float *stats;
+    float *grad_f, *grad_u;  // grad_u may equal grad_f (sum written)
+};
+
+// Number of blocks (= partial sums) of the generic energy pass.
+int64_t energy_blocks_generic(const Geo &g);
+
+hipError_t launch_fwd_generic(const Geo &g, int dtype, int mode, const FwdArgs &a,
+                              hipStream_t s);
+hipError_t launch_grad_exact_generic(const Geo &g, int dtype, const GradArgs &a,
+                                     hipStream_t s);
+hipError_t launch_energy_final(const dfloat *partial, int64_t n, float *e_out,
+                               hipStream_t s);
+
+}  // namespace tnlm

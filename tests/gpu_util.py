@@ -1,0 +1,62 @@
+"""Helpers shared by the GPU parity tests (inputs, tolerances, comparisons)."""
+import sys
+
+import numpy as np
+import torch
+
+from phantom import quantise, random_volumes, scaled_phantom
+
+TORCH_DT = {"f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}
+# half a unit in the last place, relative, of each storage format
+STORE_EPS = {"f32": 0.0, "bf16": 2.0 ** -8, "f16": 2.0 ** -11}
+FP32_TOL = 1e-5  # normwise relative tolerance of FP32 outputs vs the oracle
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def device():
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    return torch.device("cuda", 0)
+
+
+def to_dev(x64, storage="f32"):
+    """(float64 values the oracle sees, device tensor in storage dtype)."""
+    q, raw = quantise(x64, storage)
+    if storage == "bf16":
+        t = torch.from_numpy(raw.view(np.int16).copy()).view(torch.bfloat16)
+    else:
+        t = torch.from_numpy(np.ascontiguousarray(raw))
+    return q, t.to(device())
+
+
+def host(t):
+    return t.float().cpu().numpy().astype(np.float64)
+
+
+def normwise(got, ref):
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    scale = np.abs(ref).max()
+    err = np.abs(got - ref).max()
+    return err / scale if scale > 0 else err
+
+
+def assert_close(got, ref, tol, what):
+    e = normwise(got, ref)
+    say(f"  {what}: normwise rel err {e:.3e} (tol {tol:.1e})")
+    assert np.isfinite(np.asarray(got)).all(), f"{what}: non-finite output"
+    assert e <= tol, f"{what}: normwise rel err {e:.3e} > {tol:.1e}"
+
+
+def inputs(shape, kind, seed):
+    """Seeded float64 volumes of a given flavour."""
+    if kind == "phantom":
+        return scaled_phantom(shape, seed)
+    if kind == "uniform":
+        return random_volumes(shape, seed, scale=0.3)
+    if kind == "smooth":  # mild contrast: a well-conditioned case
+        return 0.2 + random_volumes(shape, seed, scale=0.02)
+    raise ValueError(kind)

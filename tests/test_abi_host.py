@@ -1,0 +1,153 @@
+"""Host-side checks of the C ABI: the library loads, exports every function
+include/tnlm.h declares, and rejects bad arguments before launching anything.
+
+Every call here fails validation, so no kernel is launched and no device is
+touched: the pointers are never dereferenced on the host.
+"""
+import ctypes
+
+import pytest
+
+from paper_1201_2450_amd import _lib
+from paper_1201_2450_amd._lib import Geom, lib
+
+FAKE = 0x10000          # never dereferenced: validation fails first
+FAKE2 = 0x20000000
+FAKE3 = 0x40000000
+
+
+def geom(np_=3, nx=8, ny=8, nz=8, d=1, M=2, h=0.05):
+    return Geom(np_, nx, ny, nz, d, M, h)
+
+
+def test_every_declared_function_is_exported():
+    names = _lib.header_functions()
+    assert set(names) >= {"tnlm_weights", "tnlm_jacobi_step", "tnlm_energy",
+                          "tnlm_grad", "tnlm_workspace_bytes",
+                          "tnlm_strerror", "tnlm_version"}
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_version_and_strerror():
+    assert lib.tnlm_version().startswith(b"tnlm")
+    for code in (0, -1, -2, -3, -4, -5, -6, -99):
+        assert isinstance(lib.tnlm_strerror(code), bytes)
+
+
+@pytest.mark.parametrize("g", [
+    geom(np_=1), geom(np_=0), geom(nx=0), geom(nz=-3), geom(d=-1), geom(M=-1),
+    geom(d=9), geom(M=17), geom(h=0.0), geom(h=-1.0), geom(h=float("nan")),
+    geom(h=float("inf")), geom(h=1e-30),
+])
+def test_bad_geometry_is_einval(g):
+    rc = lib.tnlm_jacobi_step(ctypes.byref(g), 0, FAKE, FAKE, FAKE, 1.0,
+                              FAKE2, None)
+    assert rc == _lib.EINVAL
+    assert lib.tnlm_workspace_bytes(ctypes.byref(g), _lib.OP_ENERGY) == \
+        ctypes.c_size_t(-1).value
+
+
+def test_null_geometry():
+    assert lib.tnlm_jacobi_step(None, 0, FAKE, FAKE, FAKE, 1.0, FAKE2,
+                                None) == _lib.ENULL
+
+
+def test_size_overflow_is_erange():
+    g = geom(nx=2048, ny=2048, nz=1024)  # 2^32 voxels per phase
+    assert lib.tnlm_jacobi_step(ctypes.byref(g), 0, FAKE, FAKE, FAKE, 1.0,
+                                FAKE2, None) == _lib.ERANGE
+
+
+def test_total_voxel_count_overflow_is_erange():
+    g = geom(np_=2048, nx=1024, ny=1024, nz=1024)  # 2^41 voxels in all
+    assert lib.tnlm_weights(ctypes.byref(g), 0, FAKE, FAKE2, None,
+                            None) == _lib.ERANGE
+
+
+def test_jacobi_argument_checks():
+    g = geom()
+    call = lambda dt=0, u=FAKE, f=FAKE, gg=FAKE, mu=1.0, out=FAKE2: \
+        lib.tnlm_jacobi_step(ctypes.byref(g), dt, u, f, gg, mu, out, None)
+    assert call(dt=3) == _lib.EINVAL
+    assert call(dt=-1) == _lib.EINVAL
+    assert call(mu=0.0) == _lib.EINVAL
+    assert call(mu=-1.0) == _lib.EINVAL
+    assert call(mu=float("nan")) == _lib.EINVAL
+    assert call(u=None) == _lib.ENULL
+    assert call(f=None) == _lib.ENULL
+    assert call(gg=None) == _lib.ENULL
+    assert call(out=None) == _lib.ENULL
+    # output overlapping an input: same pointer, or a partial overlap
+    assert call(out=FAKE) == _lib.EALIAS
+    assert call(out=FAKE + 64) == _lib.EALIAS
+    assert call(f=FAKE3, out=FAKE3 - 16) == _lib.EALIAS
+
+
+def test_weights_argument_checks():
+    g = geom()
+    assert lib.tnlm_weights(ctypes.byref(g), 0, FAKE, None, None, None) == \
+        _lib.ENULL
+    assert lib.tnlm_weights(ctypes.byref(g), 0, None, FAKE2, None, None) == \
+        _lib.ENULL
+    assert lib.tnlm_weights(ctypes.byref(g), 5, FAKE, FAKE2, None, None) == \
+        _lib.EINVAL
+    assert lib.tnlm_weights(ctypes.byref(g), 0, FAKE, FAKE, None, None) == \
+        _lib.EALIAS
+    assert lib.tnlm_weights(ctypes.byref(g), 0, FAKE, FAKE2, FAKE2 + 4,
+                            None) == _lib.EALIAS
+
+
+def test_energy_argument_checks():
+    g = geom()
+    need = lib.tnlm_workspace_bytes(ctypes.byref(g), _lib.OP_ENERGY)
+    assert need > 0
+    e = lambda u=FAKE, f=FAKE, eo=FAKE2, st=None, ws=FAKE3, n=need: \
+        lib.tnlm_energy(ctypes.byref(g), 0, u, f, eo, st, ws, n, None)
+    assert e(eo=None) == _lib.ENULL
+    assert e(u=None) == _lib.ENULL
+    assert e(ws=None) == _lib.EWORKSPACE
+    assert e(n=need - 1) == _lib.EWORKSPACE
+    assert e(eo=FAKE) == _lib.EALIAS
+    assert e(ws=FAKE2) == _lib.EALIAS
+
+
+def test_grad_argument_checks():
+    g = geom()
+    need = lib.tnlm_workspace_bytes(ctypes.byref(g), _lib.OP_GRAD_EXACT)
+    stats_bytes = 16 * 3 * 512
+    G = lambda u=FAKE, f=FAKE, mode=1, st=None, gf=FAKE2, gu=None, ws=FAKE3, \
+        n=need + stats_bytes: lib.tnlm_grad(ctypes.byref(g), 0, u, f, mode,
+                                            st, gf, gu, ws, n, None)
+    assert G(mode=2) == _lib.EINVAL
+    assert G(mode=0, gu=FAKE2 + 1 << 20) == _lib.EINVAL   # grad_u with EQ6
+    assert G(gf=None, gu=None) == _lib.ENULL
+    assert G(f=None) == _lib.ENULL
+    # total gradient (grad_u == grad_f) needs u == f
+    assert G(u=FAKE, f=FAKE + 4096 * 16, gu=FAKE2) == _lib.EINVAL
+    # recomputing the statistics needs the larger workspace
+    assert G(n=need) == _lib.EWORKSPACE
+    assert G(ws=None) == _lib.EWORKSPACE
+    assert G(gf=FAKE) == _lib.EALIAS
+    assert G(ws=FAKE2) == _lib.EALIAS
+    assert G(gf=FAKE2, gu=FAKE2 + 8) == _lib.EALIAS
+
+
+def test_workspace_sizes():
+    g = geom()
+    assert lib.tnlm_workspace_bytes(ctypes.byref(g), _lib.OP_JACOBI) == 0
+    assert lib.tnlm_workspace_bytes(ctypes.byref(g), _lib.OP_WEIGHTS) == 0
+    assert lib.tnlm_workspace_bytes(ctypes.byref(g), _lib.OP_GRAD_EQ6) == 0
+    assert lib.tnlm_workspace_bytes(ctypes.byref(g), 99) == \
+        ctypes.c_size_t(-1).value
+    a = lib.tnlm_workspace_bytes(ctypes.byref(g), _lib.OP_ENERGY)
+    assert a % 256 == 0 and a >= 8
+
+
+def test_package_has_no_cpu_path():
+    import torch
+
+    import paper_1201_2450_amd as tnlm
+    x = torch.zeros((2, 4, 4, 4))
+    with pytest.raises(ValueError, match="GPU"):
+        tnlm.jacobi_step(x, x, x, 1.0, d=1, M=1, h=0.1)

@@ -1,0 +1,174 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Each case draws seeded inputs, rounds them to the storage dtype, runs the
+oracle on exactly those values and the library on the device, and compares
+element by element (normwise relative error), at sizes the oracle finishes in
+seconds that still span several tiles and ragged tails. Tolerances: FP32
+outputs 1e-5; volumes stored in BF16/FP16 additionally half a storage ulp.
+"""
+import itertools
+
+import numpy as np
+import pytest
+import torch
+
+import paper_1201_2450_amd as tnlm
+from oracle import oracle
+from tests.gpu_util import (FP32_TOL, STORE_EPS, assert_close, device, host,
+                            inputs, say, to_dev)
+
+pytestmark = pytest.mark.gpu
+
+# (shape, d, M, h, kind): ragged shapes, borders on every side, d/M spread
+CASES = [
+    ((3, 13, 11, 37), 1, 2, 0.05, "phantom"),
+    ((2, 9, 10, 70), 1, 3, 0.04, "phantom"),
+    ((4, 7, 6, 5), 0, 1, 0.1, "smooth"),
+    ((3, 6, 17, 9), 2, 2, 0.08, "phantom"),
+    ((2, 5, 5, 5), 1, 4, 0.3, "uniform"),
+    ((5, 8, 3, 129), 1, 1, 0.05, "phantom"),
+    ((3, 1, 9, 33), 1, 2, 0.05, "phantom"),    # nx = 1
+    ((2, 4, 4, 1), 1, 2, 0.2, "uniform"),      # nz = 1
+    ((3, 12, 10, 20), 1, 2, 0.03, "uniform"),  # deep-underflow / overflow path
+    ((2, 6, 7, 8), 1, 0, 0.05, "phantom"),     # M = 0: single candidate
+]
+
+
+def ids(c):
+    return "np{}x{}x{}x{}-d{}M{}-{}".format(*c[0], c[1], c[2], c[4])
+
+
+@pytest.mark.parametrize("case", CASES, ids=[ids(c) for c in CASES])
+def test_weights_and_lse(case):
+    shape, d, M, h, kind = case
+    say(f"weights {shape} d={d} M={M} h={h} {kind}")
+    u64, u = to_dev(inputs(shape, kind, 1), "f32")
+    w_ref, lse_ref = oracle.weights(u64, d, M, h)
+    w, lse = tnlm.weights(u, d=d, M=M, h=h, want_w=True)
+    torch.cuda.synchronize()
+    assert_close(host(w), w_ref, FP32_TOL, "w")
+    assert_close(host(lse), lse_ref, FP32_TOL, "lse")
+    assert np.abs(host(w).sum(axis=2) - 1).max() <= 1e-5
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16", "f16"])
+@pytest.mark.parametrize("case", CASES, ids=[ids(c) for c in CASES])
+def test_jacobi_step(case, storage):
+    shape, d, M, h, kind = case
+    say(f"jacobi {shape} d={d} M={M} h={h} {kind} {storage}")
+    u64, u = to_dev(inputs(shape, kind, 2), storage)
+    f64, f = to_dev(inputs(shape, kind, 3), storage)
+    g64, g = to_dev(inputs(shape, kind, 4), storage)
+    mu = 0.7
+    ref = oracle.jacobi(u64, f64, g64, mu, d, M, h)
+    out = tnlm.jacobi_step(u, f, g, mu, d=d, M=M, h=h)
+    torch.cuda.synchronize()
+    assert out.dtype == f.dtype
+    assert_close(host(out), ref, FP32_TOL + STORE_EPS[storage], "f_out")
+
+
+@pytest.mark.parametrize("case", CASES, ids=[ids(c) for c in CASES])
+def test_eq6_operator(case):
+    shape, d, M, h, kind = case
+    say(f"eq6 {shape} d={d} M={M} h={h} {kind}")
+    u64, u = to_dev(inputs(shape, kind, 5), "f32")
+    f64, f = to_dev(inputs(shape, kind, 6), "f32")
+    ref = oracle.grad_eq6(u64, f64, d, M, h)
+    out = tnlm.grad(f, u=u, d=d, M=M, h=h, mode="eq6")
+    torch.cuda.synchronize()
+    assert_close(host(out), ref, FP32_TOL, "G6")
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+@pytest.mark.parametrize("case", CASES, ids=[ids(c) for c in CASES])
+def test_energy_and_stats(case, storage):
+    shape, d, M, h, kind = case
+    say(f"energy {shape} d={d} M={M} h={h} {kind} {storage}")
+    u64, u = to_dev(inputs(shape, kind, 7), storage)
+    f64, f = to_dev(inputs(shape, kind, 8), storage)
+    E_ref, st_ref = oracle.energy(u64, f64, d, M, h, want_stats=True)
+    e, st = tnlm.energy(f, u=u, d=d, M=M, h=h, want_stats=True)
+    torch.cuda.synchronize()
+    E = float(e[0].item()) + float(e[1].item())
+    say(f"  E gpu {E!r} oracle {E_ref!r}")
+    assert abs(E - E_ref) <= FP32_TOL * abs(E_ref)
+    N = int(np.prod(shape[1:]))
+    st_ref = st_ref.reshape(shape[0], 2, 2, N)
+    assert_close(host(st)[:, :, 0], st_ref[:, :, 0], FP32_TOL, "stats.lse")
+    assert_close(host(st)[:, :, 1], st_ref[:, :, 1], FP32_TOL, "stats.e")
+
+
+GRAD_CASES = [c for c in CASES if np.prod(c[0]) <= 6000]
+
+
+@pytest.mark.parametrize("case", GRAD_CASES, ids=[ids(c) for c in GRAD_CASES])
+def test_exact_gradient(case):
+    shape, d, M, h, kind = case
+    say(f"grad exact {shape} d={d} M={M} h={h} {kind}")
+    u64, u = to_dev(inputs(shape, kind, 9), "f32")
+    f64, f = to_dev(inputs(shape, kind, 10), "f32")
+    gf_ref, gu_ref = oracle.grad_exact_scatter(u64, f64, d, M, h)
+    gf, gu = tnlm.grad(f, u=u, d=d, M=M, h=h, mode="exact")
+    torch.cuda.synchronize()
+    assert_close(host(gf), gf_ref, FP32_TOL, "dE/df")
+    assert_close(host(gu), gu_ref, FP32_TOL, "dE/du")
+    # total gradient of E(f; f), with saved statistics
+    e, st = tnlm.energy(f, d=d, M=M, h=h, want_stats=True)
+    gt = tnlm.grad(f, d=d, M=M, h=h, mode="exact", stats=st, total=True)
+    a, b = oracle.grad_exact_scatter(f64, f64, d, M, h)
+    torch.cuda.synchronize()
+    assert_close(host(gt), a + b, FP32_TOL, "dE/df+dE/du (u=f)")
+
+
+def test_results_are_bitwise_deterministic():
+    shape, d, M, h = (3, 16, 12, 40), 1, 2, 0.05
+    say(f"determinism {shape}")
+    _, u = to_dev(inputs(shape, "phantom", 11))
+    outs = []
+    for _ in range(2):
+        j = tnlm.jacobi_step(u, u, u, 0.5, d=d, M=M, h=h)
+        e, st = tnlm.energy(u, d=d, M=M, h=h, want_stats=True)
+        gt = tnlm.grad(u, d=d, M=M, h=h, mode="exact", stats=st, total=True)
+        torch.cuda.synchronize()
+        outs.append([t.cpu().numpy().copy() for t in (j, e, st, gt)])
+    for a, b in zip(*outs):
+        assert np.array_equal(a.view(np.uint8), b.view(np.uint8))
+
+
+def test_constant_volume_is_a_fixed_point_on_gpu():
+    shape = (3, 20, 9, 33)
+    say(f"constant fixed point {shape}")
+    c = torch.full(shape, 0.3125, device=device())
+    out = tnlm.jacobi_step(c, c, c, 0.5, d=1, M=3, h=0.04)
+    e, _ = tnlm.energy(c, d=1, M=3, h=0.04)
+    torch.cuda.synchronize()
+    assert torch.all(out == c)
+    assert float(e[0]) == 0.0 and float(e[1]) == 0.0
+
+
+def test_autograd_energy_matches_exact_gradient():
+    shape, d, M, h = (3, 6, 5, 7), 1, 2, 0.08
+    say(f"autograd {shape}")
+    f64, f = to_dev(inputs(shape, "phantom", 12))
+    x = f.clone().requires_grad_(True)
+    E = tnlm.tnlm_energy(x, d, M, h)
+    E.backward()
+    a, b = oracle.grad_exact_scatter(f64, f64, d, M, h)
+    assert abs(float(E) - oracle.energy(f64, f64, d, M, h)) <= \
+        FP32_TOL * abs(oracle.energy(f64, f64, d, M, h))
+    assert_close(host(x.grad), a + b, FP32_TOL, "autograd grad")
+
+
+def test_enhance_driver_matches_repeated_oracle_steps():
+    shape, d, M, h, mu = (3, 10, 9, 12), 1, 2, 0.05, 1.0
+    say(f"enhance driver {shape}")
+    g64, g = to_dev(inputs(shape, "phantom", 13))
+    out = tnlm.enhance(g, mu, d=d, M=M, h=h, iters=3, recompute_every=2)
+    f = g64.copy()
+    u = g64
+    for k in range(3):
+        if k % 2 == 0:
+            u = f.copy()
+        f = oracle.jacobi(u, f, g64, mu, d, M, h)
+    torch.cuda.synchronize()
+    assert_close(host(out), f, 3 * FP32_TOL, "enhance(3 steps)")
