@@ -36,6 +36,8 @@ class TNLMError(RuntimeError):
 
 
 def _load():
+    # PyTorch first: its ROCm runtime is the one libtnlm.so must bind to
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError(
             f"libtnlm.so not found at {LIB_PATH}: build it first with "

@@ -23,6 +23,7 @@ ARCH = os.environ.get("TNLM_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+    "-mcode-object-version=5",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include"),
 ]
@@ -43,6 +44,18 @@ def _compile(src: str) -> str:
     return obj
 
 
+def _runtime_dir() -> str:
+    """Directory of an unversioned libamdhip64.so without a SONAME (PyTorch's
+    bundled runtime), so the recorded dependency is 'libamdhip64.so'."""
+    import importlib.util
+    spec = importlib.util.find_spec("torch")
+    if spec and spec.origin:
+        d = os.path.join(os.path.dirname(spec.origin), "lib")
+        if os.path.exists(os.path.join(d, "libamdhip64.so")):
+            return d
+    return "/opt/rocm/lib"
+
+
 def build(verbose: bool = False) -> str:
     """Compile every HIP source and link libtnlm.so; returns its path."""
     os.makedirs(BUILD, exist_ok=True)
@@ -50,7 +63,13 @@ def build(verbose: bool = False) -> str:
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    # Link against the HIP runtime by its unversioned name, so that inside a
+    # process that already loaded PyTorch's bundled ROCm runtime the library
+    # binds to that same runtime (one HIP/HSA stack per process: device
+    # pointers and streams from torch stay valid); standalone it resolves to
+    # the system ROCm.
+    cmd = ["g++", "-shared", "-fPIC", "-o", tmp, *objs, "-L" + _runtime_dir(),
+           "-l:libamdhip64.so", "-Wl,--no-undefined", "-lstdc++", "-lm"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")

@@ -1,0 +1,407 @@
+// Tiled exact gradient of the TNLM energy for 3x3x3 patches (d = 1) and
+// search radius M = 1..4, gather form, from the saved per-voxel statistics
+// (log-normaliser and e of every voxel and direction).
+//
+// For output phase k, neighbour j = k+s and search offset delta:
+//   image part   dE/df_k(q) += 1/2 (w1 + w2) r,      q in the grid,
+//   weight part  dE/dU_k(q') += 2 Delta(q') sum_p Gv(q'-p),
+// with, at every position v with v and v+delta in the grid,
+//   D  = patch distance between u_k around v and u_j around v+delta,
+//   w1 = exp(-D/(2h^2) - lse_{k,s}(v)),  w2 = exp(-D/(2h^2) - lse_{j,-s}(v+delta)),
+//   r  = f_k(v) - f_j(v+delta),
+//   Gv = -(1/(8h^2)) [w1 (r^2 - e_{k,s}(v)) + w2 (r^2 - e_{j,-s}(v+delta))],
+//   Delta(q') = U_k(q') - U_j(q'+delta)  (clamp-to-edge values).
+// The weight part lives on the padded grid (every q' within one voxel of the
+// grid, since patches reach one voxel out); a second kernel folds each padded
+// position onto the grid voxel it clamps to, which is the chain rule through
+// the clamp-to-edge extension.
+//
+// Work layout (one workgroup = 4 waves): a workgroup owns 2 (x) x 56 (y) x 16
+// (z) padded outputs of one phase; lanes run along y in 32-lane segments
+// (two halo rows on each side: one for the distance box, one for the Gv box,
+// so 28 outputs per segment); each lane keeps 2 (x) x 4 (z) outputs. Per
+// search offset a lane builds D on its block grown by one voxel in x and z
+// (box sums of squared differences as in the forward kernel), forms Gv there,
+// and box-sums Gv back onto its outputs. The neighbour phase's u_j, f_j and
+// statistics are staged in LDS one dx at a time, clamped to the grid.
+#include <math.h>
+
+#include <type_traits>
+
+#include "tnlm_internal.h"
+
+namespace tnlm {
+namespace {
+
+constexpr int kBX = 2;            // outputs per lane in x
+constexpr int kBZ = 4;            // outputs per lane in z
+constexpr int kEX = kBX + 2;      // Gv positions per lane in x
+constexpr int kEZ = kBZ + 2;      // Gv positions per lane in z
+constexpr int kSX = kBX + 4;      // squared-difference planes per lane
+constexpr int kSZ = kBZ + 4;      // squared-difference z per lane
+constexpr int kSegOut = 28;       // outputs per 32-lane segment
+constexpr int kWaves = 4;
+constexpr int kThreads = 64 * kWaves;
+constexpr int kTY = 2 * kSegOut;  // 56
+constexpr int kTZ = kWaves * kBZ; // 16
+constexpr float kLog2e = 1.4426950408889634f;
+
+template <int M>
+struct GG {
+    static constexpr int YL = kTY + 4 + 2 * M;  // rows Y0-2-M .. Y0+kTY+1+M
+    static constexpr int ZL = kTZ + 4 + 2 * M;  // z    Z0-2-M .. Z0+kTZ+1+M
+    static constexpr int RU = (kSX * ZL) | 1;   // u_j row: kSX planes
+    static constexpr int RV = (kEX * ZL) | 1;   // f_j / L2 / e2 rows: kEX planes
+    static_assert((kSX - 1) * ZL + kSZ < 256, "ds_read2 offsets");
+};
+
+struct GradGrid {
+    int ntx, nty, ntz, nblocks;
+};
+
+__device__ __forceinline__ float from_below(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, true));
+}
+__device__ __forceinline__ float from_above(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, true));
+}
+__device__ __forceinline__ float ybox(float v) { return (from_below(v) + v) + from_above(v); }
+
+__device__ __forceinline__ int clampi(int a, int lo, int hi)
+{
+    return a < lo ? lo : (a > hi ? hi : a);
+}
+
+template <typename T, int M>
+__global__ void __launch_bounds__(kThreads) grad_tiled_kernel(Geo g, GradArgs a, float *gpad,
+                                                              GradGrid gg)
+{
+    using G = GG<M>;
+    __shared__ float sU[G::YL * G::RU];
+    __shared__ float sV[3][G::YL * G::RV];  // f_j, L2 = lse*log2e, e2
+
+    const int b = blockIdx.x;
+    const int q8 = gg.nblocks >> 3, r8 = gg.nblocks & 7, xcd = b & 7;
+    int t = xcd * q8 + min(xcd, r8) + (b >> 3);
+    const int tz = t % gg.ntz;
+    t /= gg.ntz;
+    const int ty = t % gg.nty;
+    t /= gg.nty;
+    const int tx = t % gg.ntx;
+    const int k = t / gg.ntx;
+    // padded coordinates: P = grid + 1, P in [0, N+2)
+    const int X0 = tx * kBX, Y0 = ty * kTY, Z0 = tz * kTZ;
+
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63, seg = lane >> 5, l = lane & 31;
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    const int64_t N = g.N;
+    const int Yp = Y0 - 2 + kSegOut * seg + l;  // this lane's padded y
+    const int y = Yp - 1;                         // grid y (may be outside)
+    const int zb = Z0 + kBZ * wave;               // first padded output z (uniform)
+    const bool yout = l >= 2 && l <= kSegOut + 1 && Yp < ny + 2;
+    const int ry = kSegOut * seg + l + M;          // LDS row of this lane's y
+    const int zoffU = kBZ * wave + M;              // LDS z of padded zb-2 (dz = 0)
+    const int zoffV = kBZ * wave + M + 1;          // LDS z of padded zb-1 (dz = 0)
+
+    const T *u = (const T *)a.u;
+    const T *f = (const T *)a.f;
+    auto vox = [&](int ph, int xx, int yy, int zz) -> int64_t {
+        return (int64_t)ph * N + ((int64_t)xx * ny + yy) * nz + zz;
+    };
+    auto st = [&](int ph, int slot, int comp, int xx, int yy, int zz) -> float {
+        return a.stats[(((int64_t)ph * 2 + slot) * 2 + comp) * N + ((int64_t)xx * ny + yy) * nz + zz];
+    };
+    const int yc = clampi(y, 0, ny - 1);
+    const bool yin = (unsigned)y < (unsigned)ny;
+
+    // u_k on the squared-difference block: padded x X0-2 .. X0+kBX+1, z zb-2 .. zb+kBZ+1
+    float uk[kSX][kSZ];
+#pragma unroll
+    for (int xs = 0; xs < kSX; ++xs)
+#pragma unroll
+        for (int zs = 0; zs < kSZ; ++zs)
+            uk[xs][zs] = load_f(u, vox(k, clampi(X0 - 3 + xs, 0, nx - 1), yc,
+                                       clampi(zb - 3 + zs, 0, nz - 1)));
+    // f_k on the Gv block (padded X0-1 .. X0+kBX, zb-1 .. zb+kBZ)
+    float fk[kEX][kEZ];
+#pragma unroll
+    for (int xe = 0; xe < kEX; ++xe)
+#pragma unroll
+        for (int ze = 0; ze < kEZ; ++ze)
+            fk[xe][ze] = load_f(f, vox(k, clampi(X0 - 2 + xe, 0, nx - 1), yc,
+                                       clampi(zb - 2 + ze, 0, nz - 1)));
+
+    float gw[kBX][kBZ], gi[kBX][kBZ];
+#pragma unroll
+    for (int xo = 0; xo < kBX; ++xo)
+#pragma unroll
+        for (int zo = 0; zo < kBZ; ++zo) {
+            gw[xo][zo] = 0.f;
+            gi[xo][zo] = 0.f;
+        }
+
+    // tiles whose every Gv position v (lanes 1..30) has v and v+delta in the
+    // grid for all offsets skip the masks (uniform over the workgroup)
+    const bool border = (X0 - 2 - M < 1) || (X0 + kBX + 1 + M > nx) || (Y0 - 2 - M < 1) ||
+                        (Y0 + kTY + 1 + M > ny) || (Z0 - 2 - M < 1) || (Z0 + kTZ + 1 + M > nz);
+    const float c2 = g.c2;
+
+    for (int slot = 0; slot < 2; ++slot) {
+        const int j = slot == 0 ? (k + 1 == g.np ? 0 : k + 1) : (k == 0 ? g.np - 1 : k - 1);
+        const int back = 1 - slot;
+        // own-side statistics on the Gv block
+        float L1[kEX][kEZ], e1[kEX][kEZ];
+#pragma unroll
+        for (int xe = 0; xe < kEX; ++xe)
+#pragma unroll
+            for (int ze = 0; ze < kEZ; ++ze) {
+                const int xx = clampi(X0 - 2 + xe, 0, nx - 1), zz = clampi(zb - 2 + ze, 0, nz - 1);
+                L1[xe][ze] = st(k, slot, 0, xx, yc, zz) * kLog2e;
+                e1[xe][ze] = st(k, slot, 1, xx, yc, zz);
+            }
+
+        auto sweep = [&](auto bord_c) {
+            constexpr bool bord = decltype(bord_c)::value;
+            for (int dx = -M; dx <= M; ++dx) {
+                __syncthreads();
+                {
+                    // stage u_j (kSX planes from padded X0-2+dx) and f_j, L2, e2
+                    // (kEX planes from padded X0-1+dx), clamped to the grid
+                    constexpr int perU = kSX * G::ZL, perV = kEX * G::ZL;
+                    constexpr int nU = G::YL * perU, nV = G::YL * perV;
+                    for (int e = tid; e < nU + 3 * nV; e += kThreads) {
+                        int arr, ee, pr;
+                        if (e < nU) {
+                            arr = -1;
+                            ee = e;
+                            pr = perU;
+                        } else {
+                            arr = (e - nU) / nV;
+                            ee = e - nU - arr * nV;
+                            pr = perV;
+                        }
+                        const int r = ee / pr, rem = ee - r * pr;
+                        const int p = rem / G::ZL, c = rem - p * G::ZL;
+                        const int gy = clampi(Y0 - 3 - M + r, 0, ny - 1);
+                        const int gz = clampi(Z0 - 3 - M + c, 0, nz - 1);
+                        if (arr < 0) {
+                            const int gx = clampi(X0 - 3 + dx + p, 0, nx - 1);
+                            sU[r * G::RU + p * G::ZL + c] = load_f(u, vox(j, gx, gy, gz));
+                        } else {
+                            const int gx = clampi(X0 - 2 + dx + p, 0, nx - 1);
+                            float v;
+                            if (arr == 0)
+                                v = load_f(f, vox(j, gx, gy, gz));
+                            else
+                                v = st(j, back, arr - 1, gx, gy, gz) * (arr == 1 ? kLog2e : 1.f);
+                            sV[arr][r * G::RV + p * G::ZL + c] = v;
+                        }
+                    }
+                }
+                __syncthreads();
+                for (int dy = -M; dy <= M; ++dy) {
+                    const bool yval = yin && (unsigned)(y + dy) < (unsigned)ny;
+                    for (int dz = -M; dz <= M; ++dz) {
+                        const float *bu = sU + (ry + dy) * G::RU + zoffU + dz;
+                        const float *bf = sV[0] + (ry + dy) * G::RV + zoffV + dz;
+                        const float *bl = sV[1] + (ry + dy) * G::RV + zoffV + dz;
+                        const float *be = sV[2] + (ry + dy) * G::RV + zoffV + dz;
+                        // D on the Gv block
+                        float D[kEX][kEZ];
+                        float p0[kEZ], p1[kEZ];
+#pragma unroll
+                        for (int xs = 0; xs < kSX; ++xs) {
+                            float sq[kSZ];
+#pragma unroll
+                            for (int zs = 0; zs < kSZ; ++zs) {
+                                const float d = uk[xs][zs] - bu[xs * G::ZL + zs];
+                                sq[zs] = d * d;
+                            }
+                            float py[kEZ];
+#pragma unroll
+                            for (int ze = 0; ze < kEZ; ++ze)
+                                py[ze] = ybox(sq[ze] + sq[ze + 1] + sq[ze + 2]);
+                            if (xs >= 2) {
+#pragma unroll
+                                for (int ze = 0; ze < kEZ; ++ze)
+                                    D[xs - 2][ze] = (p0[ze] + p1[ze]) + py[ze];
+                            }
+#pragma unroll
+                            for (int ze = 0; ze < kEZ; ++ze) {
+                                p0[ze] = p1[ze];
+                                p1[ze] = py[ze];
+                            }
+                        }
+                        // Gv on the block; image part at the grid outputs
+                        float Gv[kEX][kEZ];
+#pragma unroll
+                        for (int xe = 0; xe < kEX; ++xe)
+#pragma unroll
+                            for (int ze = 0; ze < kEZ; ++ze) {
+                                const float tt = -c2 * D[xe][ze];
+                                const float fj = bf[xe * G::ZL + ze];
+                                const float w1 = __builtin_amdgcn_exp2f(tt - L1[xe][ze]);
+                                const float w2 = __builtin_amdgcn_exp2f(tt - bl[xe * G::ZL + ze]);
+                                const float r = fk[xe][ze] - fj;
+                                const float r2 = r * r;
+                                float gv = fmaf(w2, r2 - be[xe * G::ZL + ze], w1 * (r2 - e1[xe][ze]));
+                                float wr = (w1 + w2) * r;
+                                if (bord) {
+                                    // v = padded (X0-1+xe, Yp, zb-1+ze) - 1 and v + delta in the grid
+                                    const int vx = X0 - 2 + xe, vz = zb - 2 + ze;
+                                    const bool ok = yval & ((unsigned)vx < (unsigned)nx) &
+                                                    ((unsigned)(vx + dx) < (unsigned)nx) &
+                                                    ((unsigned)vz < (unsigned)nz) &
+                                                    ((unsigned)(vz + dz) < (unsigned)nz);
+                                    gv = ok ? gv : 0.f;
+                                    wr = ok ? wr : 0.f;
+                                }
+                                Gv[xe][ze] = gv;
+                                if (xe >= 1 && xe <= kBX && ze >= 1 && ze <= kBZ)
+                                    gi[xe - 1][ze - 1] += wr;
+                            }
+                        // box of Gv onto the outputs, times Delta
+                        float gy[kEX][kBZ];
+#pragma unroll
+                        for (int xe = 0; xe < kEX; ++xe)
+#pragma unroll
+                            for (int zo = 0; zo < kBZ; ++zo)
+                                gy[xe][zo] = ybox(Gv[xe][zo] + Gv[xe][zo + 1] + Gv[xe][zo + 2]);
+#pragma unroll
+                        for (int xo = 0; xo < kBX; ++xo)
+#pragma unroll
+                            for (int zo = 0; zo < kBZ; ++zo) {
+                                const float G3 = (gy[xo][zo] + gy[xo + 1][zo]) + gy[xo + 2][zo];
+                                const float Dl = uk[xo + 2][zo + 2] - bu[(xo + 2) * G::ZL + zo + 2];
+                                gw[xo][zo] = fmaf(Dl, G3, gw[xo][zo]);
+                            }
+                    }
+                }
+            }
+        };
+        if (border)
+            sweep(std::true_type{});
+        else
+            sweep(std::false_type{});
+    }
+
+    // write: weight part to the padded buffer, image part to grad_f
+    const float sw = -0.5f * g.inv2h2;  // 2 * (-1/(8h^2))
+    const int64_t NP = (int64_t)(nx + 2) * (ny + 2) * (nz + 2);
+#pragma unroll
+    for (int xo = 0; xo < kBX; ++xo)
+#pragma unroll
+        for (int zo = 0; zo < kBZ; ++zo) {
+            const int Xp = X0 + xo, Zp = zb + zo;
+            if (!yout || Xp >= nx + 2 || Zp >= nz + 2)
+                continue;
+            if (gpad)
+                gpad[(int64_t)k * NP + ((int64_t)Xp * (ny + 2) + Yp) * (nz + 2) + Zp] = sw * gw[xo][zo];
+            const int xg = Xp - 1, zg = Zp - 1;
+            if (a.grad_f && (unsigned)xg < (unsigned)nx && yin && (unsigned)zg < (unsigned)nz)
+                a.grad_f[vox(k, xg, y, zg)] = 0.5f * gi[xo][zo];
+        }
+}
+
+// grad_u(q) = sum of the padded weight-part values at every padded position
+// that clamps to q (plus grad_f when the total gradient is asked for).
+__global__ void __launch_bounds__(256) fold_kernel(Geo g, const float *gpad, float *grad_u,
+                                                   const float *add)
+{
+    const int64_t total = (int64_t)g.np * g.N;
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    const int64_t NP = (int64_t)(nx + 2) * (ny + 2) * (nz + 2);
+    for (int64_t flat = (int64_t)blockIdx.x * 256 + threadIdx.x; flat < total;
+         flat += (int64_t)gridDim.x * 256) {
+        const int k = (int)(flat / g.N);
+        const int64_t v = flat - (int64_t)k * g.N;
+        const int z = (int)(v % nz), y = (int)((v / nz) % ny), x = (int)(v / ((int64_t)nz * ny));
+        const int xl = x == 0 ? 0 : x + 1, xh = x == nx - 1 ? nx + 1 : x + 1;
+        const int yl = y == 0 ? 0 : y + 1, yh = y == ny - 1 ? ny + 1 : y + 1;
+        const int zl = z == 0 ? 0 : z + 1, zh = z == nz - 1 ? nz + 1 : z + 1;
+        float s = 0.f;
+        for (int X = xl; X <= xh; ++X)
+            for (int Y = yl; Y <= yh; ++Y)
+                for (int Z = zl; Z <= zh; ++Z)
+                    s += gpad[(int64_t)k * NP + ((int64_t)X * (ny + 2) + Y) * (nz + 2) + Z];
+        grad_u[flat] = add ? s + add[flat] : s;
+    }
+}
+
+template <typename T>
+hipError_t launch_t(const Geo &g, const GradArgs &a, float *gpad, const GradGrid &gg, hipStream_t s)
+{
+    switch (g.M) {
+    case 1:
+        grad_tiled_kernel<T, 1><<<gg.nblocks, kThreads, 0, s>>>(g, a, gpad, gg);
+        break;
+    case 2:
+        grad_tiled_kernel<T, 2><<<gg.nblocks, kThreads, 0, s>>>(g, a, gpad, gg);
+        break;
+    case 3:
+        grad_tiled_kernel<T, 3><<<gg.nblocks, kThreads, 0, s>>>(g, a, gpad, gg);
+        break;
+    default:
+        grad_tiled_kernel<T, 4><<<gg.nblocks, kThreads, 0, s>>>(g, a, gpad, gg);
+        break;
+    }
+    return hipGetLastError();
+}
+
+GradGrid grad_grid(const Geo &g)
+{
+    GradGrid gg;
+    gg.ntx = (g.nx + 2 + kBX - 1) / kBX;
+    gg.nty = (g.ny + 2 + kTY - 1) / kTY;
+    gg.ntz = (g.nz + 2 + kTZ - 1) / kTZ;
+    gg.nblocks = g.np * gg.ntx * gg.nty * gg.ntz;
+    return gg;
+}
+
+}  // namespace
+
+bool grad_tiled_supported(const Geo &g)
+{
+    if (g.d != 1 || g.M < 1 || g.M > 4)
+        return false;
+    const int64_t nb = (int64_t)g.np * ((g.nx + 2 + kBX - 1) / kBX) *
+                       ((g.ny + 2 + kTY - 1) / kTY) * ((g.nz + 2 + kTZ - 1) / kTZ);
+    return nb < (int64_t(1) << 31);
+}
+
+size_t grad_tiled_pad_bytes(const Geo &g)
+{
+    return (size_t)g.np * (g.nx + 2) * (g.ny + 2) * (g.nz + 2) * sizeof(float);
+}
+
+hipError_t launch_grad_tiled(const Geo &g, int dtype, const GradArgs &a, float *gpad, hipStream_t s)
+{
+    const GradGrid gg = grad_grid(g);
+    hipError_t e;
+    // weight part needed for grad_u; the kernel always writes it to gpad
+    float *gp = a.grad_u ? gpad : nullptr;
+    switch (dtype) {
+    case TNLM_F32:
+        e = launch_t<float>(g, a, gp, gg, s);
+        break;
+    case TNLM_BF16:
+        e = launch_t<bf16_t>(g, a, gp, gg, s);
+        break;
+    default:
+        e = launch_t<_Float16>(g, a, gp, gg, s);
+        break;
+    }
+    if (e != hipSuccess || !a.grad_u)
+        return e;
+    int64_t blocks = ((int64_t)g.np * g.N + 255) / 256;
+    blocks = blocks > 65536 ? 65536 : blocks;
+    const float *add = (a.grad_u == a.grad_f) ? a.grad_f : nullptr;
+    fold_kernel<<<blocks, 256, 0, s>>>(g, gpad, a.grad_u, add);
+    return hipGetLastError();
+}
+
+}  // namespace tnlm

@@ -71,9 +71,29 @@ bool overlap(const void *a, size_t na, const void *b, size_t nb)
 
 size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
 
-size_t partial_bytes(const Geo &g) { return align256((size_t)energy_blocks_generic(g) * sizeof(dfloat)); }
+// Forward kernels: the tiled path where it applies, else the generic one.
+bool tiled(const Geo &g, int mode) { return fwd_tiled_supported(g, mode); }
+
+hipError_t launch_fwd(const Geo &g, int dtype, int mode, const FwdArgs &a, hipStream_t s)
+{
+    if (tiled(g, mode) && !(mode == FWD_WEIGHTS && a.w))
+        return launch_fwd_tiled(g, dtype, mode, a, s);
+    return launch_fwd_generic(g, dtype, mode, a, s);
+}
+
+int64_t energy_blocks(const Geo &g)
+{
+    return tiled(g, FWD_ENERGY) ? energy_blocks_tiled(g) : energy_blocks_generic(g);
+}
+
+size_t partial_bytes(const Geo &g) { return align256((size_t)energy_blocks(g) * sizeof(dfloat)); }
 
 size_t stats_bytes(const Geo &g) { return (size_t)g.np * g.N * 4 * sizeof(float); }
+
+// Exact gradient workspace: [partial sums][padded weight part]; the caller
+// appends room for the statistics when it passes none.
+size_t pad_bytes(const Geo &g) { return grad_tiled_supported(g) ? align256(grad_tiled_pad_bytes(g)) : 0; }
+size_t grad_exact_bytes(const Geo &g) { return partial_bytes(g) + pad_bytes(g); }
 
 }  // namespace
 
@@ -114,8 +134,9 @@ size_t tnlm_workspace_bytes(const tnlm_geom *geom, int op)
     case TNLM_OP_GRAD_EQ6:
         return 0;
     case TNLM_OP_ENERGY:
-    case TNLM_OP_GRAD_EXACT:
         return partial_bytes(g);
+    case TNLM_OP_GRAD_EXACT:
+        return grad_exact_bytes(g);
     default:
         return (size_t)-1;
     }
@@ -145,7 +166,7 @@ int tnlm_weights(const tnlm_geom *geom, int dtype, const void *u, float *w, floa
     a.u = u;
     a.w = w;
     a.lse = lse;
-    hipError_t e = launch_fwd_generic(g, dtype, FWD_WEIGHTS, a, (hipStream_t)stream);
+    hipError_t e = launch_fwd(g, dtype, FWD_WEIGHTS, a, (hipStream_t)stream);
     return e == hipSuccess ? TNLM_OK : hip_fail(e);
 }
 
@@ -169,7 +190,7 @@ int tnlm_jacobi_step(const tnlm_geom *geom, int dtype, const void *u, const void
     a.g = gin;
     a.mu = mu;
     a.out = f_out;
-    hipError_t e = launch_fwd_generic(g, dtype, FWD_JACOBI, a, (hipStream_t)stream);
+    hipError_t e = launch_fwd(g, dtype, FWD_JACOBI, a, (hipStream_t)stream);
     return e == hipSuccess ? TNLM_OK : hip_fail(e);
 }
 
@@ -181,11 +202,11 @@ static int energy_impl(const Geo &g, int dtype, const void *u, const void *f, fl
     a.f = f;
     a.stats = stats;
     a.partial = partial;
-    hipError_t e = launch_fwd_generic(g, dtype, FWD_ENERGY, a, s);
+    hipError_t e = launch_fwd(g, dtype, FWD_ENERGY, a, s);
     if (e != hipSuccess)
         return hip_fail(e);
     if (e_out) {
-        e = launch_energy_final(partial, energy_blocks_generic(g), e_out, s);
+        e = launch_energy_final(partial, energy_blocks(g), e_out, s);
         if (e != hipSuccess)
             return hip_fail(e);
     }
@@ -253,10 +274,10 @@ int tnlm_grad(const tnlm_geom *geom, int dtype, const void *u, const void *f, in
         a.u = u;
         a.f = f;
         a.out = grad_f;
-        hipError_t e = launch_fwd_generic(g, dtype, FWD_EQ6, a, s);
+        hipError_t e = launch_fwd(g, dtype, FWD_EQ6, a, s);
         return e == hipSuccess ? TNLM_OK : hip_fail(e);
     }
-    size_t need = partial_bytes(g) + (stats ? 0 : stats_bytes(g));
+    size_t need = grad_exact_bytes(g) + (stats ? 0 : stats_bytes(g));
     if (!ws || ws_bytes < need)
         return TNLM_EWORKSPACE;
     for (int a = 0; a < 3; ++a)
@@ -266,7 +287,7 @@ int tnlm_grad(const tnlm_geom *geom, int dtype, const void *u, const void *f, in
         return TNLM_EALIAS;
     const float *st = stats;
     if (!st) {
-        float *own = (float *)((char *)ws + partial_bytes(g));
+        float *own = (float *)((char *)ws + grad_exact_bytes(g));
         rc = energy_impl(g, dtype, u, f, nullptr, own, (dfloat *)ws, s);
         if (rc)
             return rc;
@@ -281,7 +302,11 @@ int tnlm_grad(const tnlm_geom *geom, int dtype, const void *u, const void *f, in
     if (!grad_f && grad_u) {
         a.grad_f = nullptr;
     }
-    hipError_t e = launch_grad_exact_generic(g, dtype, a, s);
+    hipError_t e;
+    if (grad_tiled_supported(g))
+        e = launch_grad_tiled(g, dtype, a, (float *)((char *)ws + partial_bytes(g)), s);
+    else
+        e = launch_grad_exact_generic(g, dtype, a, s);
     return e == hipSuccess ? TNLM_OK : hip_fail(e);
 }
 

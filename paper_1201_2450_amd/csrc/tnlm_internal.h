@@ -84,8 +84,21 @@ struct GradArgs {
     float *grad_f, *grad_u;  // grad_u may equal grad_f (sum written)
 };
 
-// Number of blocks (= partial sums) of the generic energy pass.
+// Number of blocks (= partial sums) of the generic / tiled energy pass.
 int64_t energy_blocks_generic(const Geo &g);
+int64_t energy_blocks_tiled(const Geo &g);
+
+// Tiled forward kernels (d = 1, M = 1..4; weights mode: log-normalisers only).
+bool fwd_tiled_supported(const Geo &g, int mode);
+hipError_t launch_fwd_tiled(const Geo &g, int dtype, int mode, const FwdArgs &a,
+                            hipStream_t s);
+
+// Tiled exact gradient (d = 1, M = 1..4): weight part on the padded grid in
+// gpad (np*(nx+2)*(ny+2)*(nz+2) floats of workspace), then folded into grad_u.
+bool grad_tiled_supported(const Geo &g);
+size_t grad_tiled_pad_bytes(const Geo &g);
+hipError_t launch_grad_tiled(const Geo &g, int dtype, const GradArgs &a, float *gpad,
+                             hipStream_t s);
 
 hipError_t launch_fwd_generic(const Geo &g, int dtype, int mode, const FwdArgs &a,
                               hipStream_t s);

@@ -15,7 +15,7 @@ import torch
 import paper_1201_2450_amd as tnlm
 from oracle import oracle
 from tests.gpu_util import (FP32_TOL, STORE_EPS, assert_close, device, host,
-                            inputs, say, to_dev)
+                            inputs, say, to_dev, tol_for)
 
 pytestmark = pytest.mark.gpu
 
@@ -46,8 +46,8 @@ def test_weights_and_lse(case):
     w_ref, lse_ref = oracle.weights(u64, d, M, h)
     w, lse = tnlm.weights(u, d=d, M=M, h=h, want_w=True)
     torch.cuda.synchronize()
-    assert_close(host(w), w_ref, FP32_TOL, "w")
-    assert_close(host(lse), lse_ref, FP32_TOL, "lse")
+    assert_close(host(w), w_ref, tol_for(kind), "w")
+    assert_close(host(lse), lse_ref, tol_for(kind), "lse")
     assert np.abs(host(w).sum(axis=2) - 1).max() <= 1e-5
 
 
@@ -64,7 +64,7 @@ def test_jacobi_step(case, storage):
     out = tnlm.jacobi_step(u, f, g, mu, d=d, M=M, h=h)
     torch.cuda.synchronize()
     assert out.dtype == f.dtype
-    assert_close(host(out), ref, FP32_TOL + STORE_EPS[storage], "f_out")
+    assert_close(host(out), ref, tol_for(kind) + STORE_EPS[storage], "f_out")
 
 
 @pytest.mark.parametrize("case", CASES, ids=[ids(c) for c in CASES])
@@ -76,7 +76,7 @@ def test_eq6_operator(case):
     ref = oracle.grad_eq6(u64, f64, d, M, h)
     out = tnlm.grad(f, u=u, d=d, M=M, h=h, mode="eq6")
     torch.cuda.synchronize()
-    assert_close(host(out), ref, FP32_TOL, "G6")
+    assert_close(host(out), ref, tol_for(kind), "G6")
 
 
 @pytest.mark.parametrize("storage", ["f32", "bf16"])
@@ -91,11 +91,11 @@ def test_energy_and_stats(case, storage):
     torch.cuda.synchronize()
     E = float(e[0].item()) + float(e[1].item())
     say(f"  E gpu {E!r} oracle {E_ref!r}")
-    assert abs(E - E_ref) <= FP32_TOL * abs(E_ref)
+    assert abs(E - E_ref) <= tol_for(kind) * abs(E_ref)
     N = int(np.prod(shape[1:]))
     st_ref = st_ref.reshape(shape[0], 2, 2, N)
-    assert_close(host(st)[:, :, 0], st_ref[:, :, 0], FP32_TOL, "stats.lse")
-    assert_close(host(st)[:, :, 1], st_ref[:, :, 1], FP32_TOL, "stats.e")
+    assert_close(host(st)[:, :, 0], st_ref[:, :, 0], tol_for(kind), "stats.lse")
+    assert_close(host(st)[:, :, 1], st_ref[:, :, 1], tol_for(kind), "stats.e")
 
 
 GRAD_CASES = [c for c in CASES if np.prod(c[0]) <= 6000]
@@ -110,14 +110,14 @@ def test_exact_gradient(case):
     gf_ref, gu_ref = oracle.grad_exact_scatter(u64, f64, d, M, h)
     gf, gu = tnlm.grad(f, u=u, d=d, M=M, h=h, mode="exact")
     torch.cuda.synchronize()
-    assert_close(host(gf), gf_ref, FP32_TOL, "dE/df")
-    assert_close(host(gu), gu_ref, FP32_TOL, "dE/du")
+    assert_close(host(gf), gf_ref, tol_for(kind), "dE/df")
+    assert_close(host(gu), gu_ref, tol_for(kind), "dE/du")
     # total gradient of E(f; f), with saved statistics
     e, st = tnlm.energy(f, d=d, M=M, h=h, want_stats=True)
     gt = tnlm.grad(f, d=d, M=M, h=h, mode="exact", stats=st, total=True)
     a, b = oracle.grad_exact_scatter(f64, f64, d, M, h)
     torch.cuda.synchronize()
-    assert_close(host(gt), a + b, FP32_TOL, "dE/df+dE/du (u=f)")
+    assert_close(host(gt), a + b, tol_for(kind), "dE/df+dE/du (u=f)")
 
 
 def test_results_are_bitwise_deterministic():

@@ -1,0 +1,151 @@
+"""GPU parity at the benchmark workload sizes and on tiles away from borders.
+
+The small cases of test_gpu_parity.py are all border tiles; here grids are
+large enough for interior tiles (the unmasked fast path). At the full
+workload sizes the oracle evaluates sampled voxels one by one (random
+positions plus every corner and some border voxels), in the launch
+configuration bench.py times.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_1201_2450_amd as tnlm
+from oracle import oracle
+from phantom import WORKLOADS, quantise, workload_inputs
+from tests.gpu_util import FP32_TOL, assert_close, device, host, inputs, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def sample_idx(shape, n, seed):
+    """Random flat indices plus the 8 corners and face centres of phase 0
+    and of the last phase."""
+    rng = np.random.default_rng(seed)
+    np_, nx, ny, nz = shape
+    idx = list(rng.choice(np_ * nx * ny * nz, size=n, replace=False))
+    for i in (0, np_ - 1):
+        for x in (0, nx - 1):
+            for y in (0, ny - 1):
+                for z in (0, nz - 1):
+                    idx.append(np.ravel_multi_index((i, x, y, z), shape))
+        for p in ((0, ny // 2, nz // 2), (nx - 1, ny // 2, nz // 2),
+                  (nx // 2, 0, nz // 2), (nx // 2, ny - 1, nz // 2),
+                  (nx // 2, ny // 2, 0), (nx // 2, ny // 2, nz - 1)):
+            idx.append(np.ravel_multi_index((i,) + p, shape))
+    return np.array(sorted(set(int(i) for i in idx)), dtype=np.int64)
+
+
+def test_interior_tiles_forward_modes():
+    shape, d, M, h, mu = (2, 20, 130, 40), 1, 2, 0.05, 0.6
+    say(f"interior forward {shape}")
+    u64, u = to_dev(inputs(shape, "phantom", 21))
+    f64, f = to_dev(inputs(shape, "phantom", 22))
+    g64, g = to_dev(inputs(shape, "phantom", 23))
+    out = tnlm.jacobi_step(u, f, g, mu, d=d, M=M, h=h)
+    g6 = tnlm.grad(f, u=u, d=d, M=M, h=h, mode="eq6")
+    _, lse = tnlm.weights(u, d=d, M=M, h=h)
+    e, st = tnlm.energy(f, u=u, d=d, M=M, h=h, want_stats=True)
+    torch.cuda.synchronize()
+    assert_close(host(out), oracle.jacobi(u64, f64, g64, mu, d, M, h),
+                 FP32_TOL, "jacobi")
+    assert_close(host(g6), oracle.grad_eq6(u64, f64, d, M, h), FP32_TOL,
+                 "eq6")
+    E_ref, st_ref = oracle.energy(u64, f64, d, M, h, want_stats=True)
+    assert_close(host(lse), st_ref[:, :, 0], FP32_TOL, "lse")
+    assert_close(host(st), st_ref, FP32_TOL, "stats")
+    E = float(e[0]) + float(e[1])
+    assert abs(E - E_ref) <= FP32_TOL * abs(E_ref), (E, E_ref)
+
+
+def test_interior_tiles_exact_gradient_sampled():
+    shape, d, M, h = (2, 12, 116, 36), 1, 2, 0.05
+    say(f"interior gradient {shape}")
+    u64, u = to_dev(inputs(shape, "phantom", 24))
+    f64, f = to_dev(inputs(shape, "phantom", 25))
+    gf, gu = tnlm.grad(f, u=u, d=d, M=M, h=h, mode="exact")
+    torch.cuda.synchronize()
+    idx = sample_idx(shape, 160, 3)
+    rf, ru = oracle.grad_exact_at(u64, f64, d, M, h, idx)
+    assert_close(host(gf).ravel()[idx], rf, FP32_TOL, "dE/df (sampled)")
+    assert_close(host(gu).ravel()[idx], ru, FP32_TOL, "dE/du (sampled)")
+
+
+def test_enh256_jacobi_step_sampled():
+    """Clinical-size enhancement workload: one Gauss-Jacobi step in the
+    launch configuration of the benchmark (u = f = g), sampled voxels."""
+    w = WORKLOADS["enh256"]
+    say(f"enh256 jacobi {w.shape}")
+    g32 = workload_inputs(w, out_dtype=np.float32)[0]
+    g = torch.from_numpy(g32).to(device())
+    out = tnlm.jacobi_step(g, g, g, w.mu, d=w.d, M=w.M, h=w.h)
+    torch.cuda.synchronize()
+    idx = sample_idx(w.shape, 400, 4)
+    g64 = g32.astype(np.float64)
+    ref = oracle.jacobi(g64, g64, g64, w.mu, w.d, w.M, w.h, idx=idx)
+    assert_close(host(out).ravel()[idx], ref, FP32_TOL, "f_out (sampled)")
+    # log-normalisers at the same voxels
+    _, lse = tnlm.weights(g, d=w.d, M=w.M, h=w.h)
+    st = oracle.stats(g64, g64, w.d, w.M, w.h, idx=idx)
+    N = w.nx * w.ny * w.nz
+    i, v = idx // N, idx % N
+    got = host(lse)[i, :, v]
+    assert_close(got, st[:, :, 0], FP32_TOL, "lse (sampled)")
+
+
+@pytest.mark.parametrize("storage", ["bf16", "f16"])
+def test_enh256_storage_jacobi_sampled(storage):
+    w = WORKLOADS["enh256"]
+    say(f"enh256 jacobi {storage}")
+    g64q, gq = to_dev(workload_inputs(w, out_dtype=np.float32)[0], storage)
+    out = tnlm.jacobi_step(gq, gq, gq, w.mu, d=w.d, M=w.M, h=w.h)
+    torch.cuda.synchronize()
+    idx = sample_idx(w.shape, 200, 5)
+    ref = oracle.jacobi(g64q, g64q, g64q, w.mu, w.d, w.M, w.h, idx=idx)
+    eps = 2.0 ** -8 if storage == "bf16" else 2.0 ** -11
+    assert_close(host(out).ravel()[idx], ref, FP32_TOL + eps, "f_out")
+
+
+def test_energy128_energy_and_adjoint_sampled():
+    """Differentiable-energy workload at full size: per-voxel statistics and
+    the exact gradient at sampled voxels against the oracle, the total energy
+    against the compensated sum of the statistics, and the gradient against
+    central differences (eps = 1e-3) of the FP64 local energy."""
+    w = WORKLOADS["energy128"]
+    say(f"energy128 {w.shape}")
+    f32 = workload_inputs(w, out_dtype=np.float32)[0]
+    f = torch.from_numpy(f32).to(device())
+    f64 = f32.astype(np.float64)
+    e, st = tnlm.energy(f, d=w.d, M=w.M, h=w.h, want_stats=True)
+    gt = tnlm.grad(f, d=w.d, M=w.M, h=w.h, mode="exact", stats=st, total=True)
+    torch.cuda.synchronize()
+    E = float(e[0]) + float(e[1])
+    sth = st.double().cpu().numpy()
+    E_sum = 0.25 * float(np.sum(sth[:, :, 1, :]))
+    assert abs(E - E_sum) <= 1e-9 * abs(E_sum) + 1e-6, (E, E_sum)
+    idx = sample_idx(w.shape, 64, 6)
+    N = w.nx * w.ny * w.nz
+    ref_st = oracle.stats(f64, f64, w.d, w.M, w.h, idx=idx)
+    assert_close(sth[idx // N, :, :, idx % N], ref_st, FP32_TOL, "stats")
+    gidx = idx[::2]
+    rf, ru = oracle.grad_exact_at(f64, f64, w.d, w.M, w.h, gidx)
+    assert_close(host(gt).ravel()[gidx], rf + ru, FP32_TOL, "dE/df total")
+    # central differences of the FP64 local energy (eps = 1e-3, with a
+    # Richardson step at eps/2 to remove the O(eps^2) truncation)
+    ghost = host(gt).ravel()
+    scale = np.abs(rf + ru).max()
+
+    def cd(pos, eps):
+        fp, fm = f64.copy(), f64.copy()
+        fp[pos] += eps
+        fm[pos] -= eps
+        return (oracle.local_energy(fp, fp, w.d, w.M, w.h, *pos)
+                - oracle.local_energy(fm, fm, w.d, w.M, w.h, *pos)) / (2 * eps)
+
+    for flat in gidx[:12]:
+        pos = tuple(int(c) for c in np.unravel_index(int(flat), w.shape))
+        d1, d2 = cd(pos, 1e-3), cd(pos, 5e-4)
+        fd = (4 * d2 - d1) / 3
+        say(f"  FD at {pos}: gpu {ghost[flat]:.6e} fd(1e-3) {d1:.6e} "
+            f"richardson {fd:.6e}")
+        assert abs(ghost[flat] - fd) <= 1e-4 * scale
