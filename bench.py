@@ -40,6 +40,26 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measured_traffic():
+    """HBM bytes per Jacobi launch from the committed rocprofv3 counter
+    summary, or None when the kernel source changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "jacobi_enh256_traffic.txt")
+    src = os.path.join(ROOT, "paper_1201_2450_amd", "csrc", "tiled_fwd.hip")
+    try:
+        kv = {}
+        for line in open(path):
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        if kv.get("source_sha256_tiled_fwd_hip") != sha:
+            return None
+        return float(kv["traffic_bytes"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(w, target_s):
     """Time the FP64 oracle on a bounded sample of the same workload: one
     Jacobi step (u = f = g) at a random sample of voxels."""
@@ -164,7 +184,8 @@ def main():
     achieved = alg_flop / (ms["jacobi"] / 1e3) / 1e12
     roofline = {"bound": "alu", "achieved": achieved,
                 "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                "frac": achieved / PEAK_FP32_TFLOPS,
+                "traffic": measured_traffic(),
                 "kernel": "tnlm_jacobi_step",
                 "algorithmic_flop_per_launch": alg_flop}
 

@@ -4,12 +4,13 @@
 // per-voxel statistics.
 //
 // Work layout (one workgroup = 4 waves = 256 lanes):
-//   * a workgroup owns an output tile of BX (x) x 60 (y) x 16 (z) voxels of
+//   * a workgroup owns an output tile of BX (x) x 30 (y) x 32 (z) voxels of
 //     one phase i and handles both neighbour phases j = i+1 and j = i-1 in
 //     turn;
 //   * lanes run along y: each half-wave is a segment of 32 consecutive rows
 //     whose outer two lanes are halo rows, so a segment produces 30 rows;
-//     the 3-tap box sum along y is two DPP adds across lanes;
+//     the 3-tap box sum along y is two DPP adds across lanes; the eight
+//     half-waves of a workgroup take the eight 4-voxel z-blocks of the tile;
 //   * every lane keeps a BX (x) x 4 (z) block of outputs in registers: the
 //     3-tap box along z is done in registers, the one along x by marching
 //     over the BX+2 x-planes of the block with a two-plane ring;
@@ -33,7 +34,7 @@
 #include "tnlm_internal.h"
 
 #ifndef TNLM_TILE_BX
-#define TNLM_TILE_BX 8  // output x-planes per lane
+#define TNLM_TILE_BX 4  // output x-planes per lane
 #endif
 
 namespace tnlm {
@@ -43,8 +44,8 @@ constexpr int kBZ = 4;              // output z per lane
 constexpr int kSegOut = 30;         // output rows per 32-lane segment
 constexpr int kWaves = 4;           // waves per workgroup (one z-block each)
 constexpr int kThreads = 64 * kWaves;
-constexpr int kTY = 2 * kSegOut;    // tile extent in y (two segments per wave)
-constexpr int kTZ = kWaves * kBZ;   // tile extent in z
+constexpr int kTY = kSegOut;        // tile extent in y (one segment)
+constexpr int kTZ = 2 * kWaves * kBZ;  // tile extent in z (one z-block per half-wave)
 constexpr float kZOverflow = 1.2676506e30f;  // 2^100
 
 template <int M, int BX>
@@ -152,12 +153,13 @@ __global__ void __launch_bounds__(kThreads) fwd_tiled_kernel(Geo g, FwdArgs a, T
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane = tid & 63;
     const int seg = lane >> 5, l = lane & 31;
-    const int y = y0 - 1 + kSegOut * seg + l;
+    const int y = y0 - 1 + l;
     const bool yuse = l >= 1 && l <= kSegOut && y < g.ny;
-    const int zb = z0 + kBZ * wave;  // first output z of this lane block (uniform)
-    const int ry = kSegOut * seg + l + M;  // LDS row of this lane's y
-    const int zoffU = kBZ * wave + M;      // LDS z of (zb - 1), for dz = 0
-    const int zoffF = kBZ * wave + M + 1;  // LDS z of zb, for dz = 0
+    const int zblk = 2 * wave + seg;       // z-block of this half-wave
+    const int zb = z0 + kBZ * zblk;        // first output z of this lane block
+    const int ry = l + M;                  // LDS row of this lane's y
+    const int zoffU = kBZ * zblk + M;      // LDS z of (zb - 1), for dz = 0
+    const int zoffF = kBZ * zblk + M + 1;  // LDS z of zb, for dz = 0
 
     const int64_t N = g.N;
     const int nx = g.nx, ny = g.ny, nz = g.nz;
@@ -203,28 +205,35 @@ __global__ void __launch_bounds__(kThreads) fwd_tiled_kernel(Geo g, FwdArgs a, T
     Acc<BX> A;
 
     // stages the u_j / f_j planes of one dx into LDS (clamped to the grid),
-    // layout [row][plane][z]
+    // layout [row][plane][z]; lanes run along z (coalesced), each lane keeps
+    // one z column, and the (row, plane) pairs are shared out by lane group
+    constexpr int kCols = 64;  // lanes per column group (>= ZL)
+    static_assert(G::ZL <= kCols, "one z column per lane");
+    const int col = tid & (kCols - 1);
+    const int grp = tid / kCols;
+    const bool col_ok = col < G::ZL;
+    const int gzc = clampi(z0 - 1 - M + col, 0, nz - 1);
     auto stage = [&](int j, int dx) {
-        constexpr int per_row_u = G::UPL * G::ZL;
-        constexpr int per_row_f = G::FPL * G::ZL;
-        constexpr int nU = G::YL * per_row_u;
-        constexpr int nAll = nU + (MODE == FWD_WEIGHTS ? 0 : G::YL * per_row_f);
-        for (int e = tid; e < nAll; e += kThreads) {
-            const bool isU = e < nU;
-            const int ee = isU ? e : e - nU;
-            const int pr = isU ? per_row_u : per_row_f;
-            const int r = ee / pr;
-            const int rem = ee - r * pr;
-            const int p = rem / G::ZL;
-            const int c = rem - p * G::ZL;
-            const int gx = clampi(isU ? x0 - 1 + dx + p : x0 + dx + p, 0, nx - 1);
+        if (!col_ok)
+            return;
+        constexpr int nGrp = kThreads / kCols;
+        const T *uj = u + (int64_t)j * N + gzc;
+        const T *fj = f + (int64_t)j * N + gzc;
+#pragma unroll 4
+        for (int rp = grp; rp < G::YL * G::UPL; rp += nGrp) {
+            const int r = rp / G::UPL, p = rp - r * G::UPL;
+            const int gx = clampi(x0 - 1 + dx + p, 0, nx - 1);
             const int gy = clampi(y0 - 1 - M + r, 0, ny - 1);
-            const int gz = clampi(z0 - 1 - M + c, 0, nz - 1);
-            const float v = load_f(isU ? u : f, vox(j, gx, gy, gz));
-            if (isU)
-                sU[r * G::RU + p * G::ZL + c] = v;
-            else
-                sF[r * G::RF + p * G::ZL + c] = v;
+            sU[r * G::RU + p * G::ZL + col] = load_f(uj, ((int64_t)gx * ny + gy) * nz);
+        }
+        if (MODE != FWD_WEIGHTS) {
+#pragma unroll 4
+            for (int rp = grp; rp < G::YL * G::FPL; rp += nGrp) {
+                const int r = rp / G::FPL, p = rp - r * G::FPL;
+                const int gx = clampi(x0 + dx + p, 0, nx - 1);
+                const int gy = clampi(y0 - 1 - M + r, 0, ny - 1);
+                sF[r * G::RF + p * G::ZL + col] = load_f(fj, ((int64_t)gx * ny + gy) * nz);
+            }
         }
     };
 

@@ -16,10 +16,13 @@
 // position onto the grid voxel it clamps to, which is the chain rule through
 // the clamp-to-edge extension.
 //
-// Work layout (one workgroup = 4 waves): a workgroup owns 2 (x) x 56 (y) x 16
+// Work layout (one workgroup = 8 waves): a workgroup owns 2 (x) x 56 (y) x 16
 // (z) padded outputs of one phase; lanes run along y in 32-lane segments
 // (two halo rows on each side: one for the distance box, one for the Gv box,
-// so 28 outputs per segment); each lane keeps 2 (x) x 4 (z) outputs. Per
+// so 28 outputs per segment); each lane keeps 2 (x) x 4 (z) outputs. Waves
+// w and w+4 own the same outputs and split the (dy, dz) offset pairs between
+// them (alternate pairs), sharing one LDS tile; their partial sums are added
+// in a fixed order at the end, so two waves per SIMD run on 124 KB of LDS. Per
 // search offset a lane builds D on its block grown by one voxel in x and z
 // (box sums of squared differences as in the forward kernel), forms Gv there,
 // and box-sums Gv back onto its outputs. The neighbour phase's u_j, f_j and
@@ -40,8 +43,8 @@ constexpr int kEZ = kBZ + 2;      // Gv positions per lane in z
 constexpr int kSX = kBX + 4;      // squared-difference planes per lane
 constexpr int kSZ = kBZ + 4;      // squared-difference z per lane
 constexpr int kSegOut = 28;       // outputs per 32-lane segment
-constexpr int kWaves = 4;
-constexpr int kThreads = 64 * kWaves;
+constexpr int kWaves = 4;             // z-blocks per workgroup
+constexpr int kThreads = 2 * 64 * kWaves;  // two waves per z-block
 constexpr int kTY = 2 * kSegOut;  // 56
 constexpr int kTZ = kWaves * kBZ; // 16
 constexpr float kLog2e = 1.4426950408889634f;
@@ -95,7 +98,9 @@ __global__ void __launch_bounds__(kThreads) grad_tiled_kernel(Geo g, GradArgs a,
     const int X0 = tx * kBX, Y0 = ty * kTY, Z0 = tz * kTZ;
 
     const int tid = threadIdx.x;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wave = wid & (kWaves - 1);  // z-block
+    const int half = wid / kWaves;        // which (dy, dz) pairs this wave takes
     const int lane = tid & 63, seg = lane >> 5, l = lane & 31;
     const int nx = g.nx, ny = g.ny, nz = g.nz;
     const int64_t N = g.N;
@@ -203,9 +208,11 @@ __global__ void __launch_bounds__(kThreads) grad_tiled_kernel(Geo g, GradArgs a,
                     }
                 }
                 __syncthreads();
-                for (int dy = -M; dy <= M; ++dy) {
+                constexpr int S = 2 * M + 1;
+                for (int pr = half; pr < S * S; pr += 2) {
+                    const int dy = pr / S - M, dz = pr - (pr / S) * S - M;
                     const bool yval = yin && (unsigned)(y + dy) < (unsigned)ny;
-                    for (int dz = -M; dz <= M; ++dz) {
+                    {
                         const float *bu = sU + (ry + dy) * G::RU + zoffU + dz;
                         const float *bf = sV[0] + (ry + dy) * G::RV + zoffV + dz;
                         const float *bl = sV[1] + (ry + dy) * G::RV + zoffV + dz;
@@ -288,6 +295,33 @@ __global__ void __launch_bounds__(kThreads) grad_tiled_kernel(Geo g, GradArgs a,
         else
             sweep(std::false_type{});
     }
+
+    // combine the two halves in a fixed order: the second wave of each pair
+    // hands its sums over through LDS, the first adds and writes
+    __syncthreads();
+    float *xfer = sU;  // the staging tile is free now
+    constexpr int kPer = 2 * kBX * kBZ;
+    static_assert(kThreads / 2 * kPer <= GG<M>::YL * GG<M>::RU, "transfer fits");
+    const int slotx = (wave * 64 + lane) * kPer;
+    if (half == 1) {
+#pragma unroll
+        for (int xo = 0; xo < kBX; ++xo)
+#pragma unroll
+            for (int zo = 0; zo < kBZ; ++zo) {
+                xfer[slotx + xo * kBZ + zo] = gw[xo][zo];
+                xfer[slotx + kBX * kBZ + xo * kBZ + zo] = gi[xo][zo];
+            }
+    }
+    __syncthreads();
+    if (half == 1)
+        return;
+#pragma unroll
+    for (int xo = 0; xo < kBX; ++xo)
+#pragma unroll
+        for (int zo = 0; zo < kBZ; ++zo) {
+            gw[xo][zo] += xfer[slotx + xo * kBZ + zo];
+            gi[xo][zo] += xfer[slotx + kBX * kBZ + xo * kBZ + zo];
+        }
 
     // write: weight part to the padded buffer, image part to grad_f
     const float sw = -0.5f * g.inv2h2;  // 2 * (-1/(8h^2))
