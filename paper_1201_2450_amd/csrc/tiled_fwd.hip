@@ -3,59 +3,70 @@
 // per-voxel log-normalisers of the weights (Eq. (3)) and the energy with its
 // per-voxel statistics.
 //
-// Work layout (one workgroup = 4 waves = 256 lanes):
-//   * a workgroup owns an output tile of BX (x) x 30 (y) x 32 (z) voxels of
+// Work layout (a workgroup of HALVES x ZB/2 waves):
+//   * a workgroup owns an output tile of BX (x) x 30 (y) x 4*ZB (z) voxels of
 //     one phase i and handles both neighbour phases j = i+1 and j = i-1 in
 //     turn;
 //   * lanes run along y: each half-wave is a segment of 32 consecutive rows
-//     whose outer two lanes are halo rows, so a segment produces 30 rows;
-//     the 3-tap box sum along y is two DPP adds across lanes; the eight
-//     half-waves of a workgroup take the eight 4-voxel z-blocks of the tile;
-//   * every lane keeps a BX (x) x 4 (z) block of outputs in registers: the
-//     3-tap box along z is done in registers, the one along x by marching
-//     over the BX+2 x-planes of the block with a two-plane ring;
+//     whose outer two lanes are halo rows, so a segment produces 30 rows; the
+//     half-waves of a wave take two of the tile's ZB 4-voxel z-blocks;
+//   * every lane keeps a BX (x) x 4 (z) block of outputs in registers;
 //   * per search offset the patch distance D(v, delta) of every output is
 //     built from per-position squared differences (d = u_i - u_j(. + delta),
-//     d*d) and the three separable box sums, never the (2d+1)^3 direct sum;
-//   * the neighbour phase's weight source u_j and image f_j are staged in
-//     LDS one x-offset (dx) at a time: BX+2 u_j planes and BX f_j planes with
-//     the y/z halo of the window, clamped to the grid (clamp-to-edge); the
-//     LDS layout is [row][plane][z] with an odd row stride, so one base
-//     address per lane serves every plane of a search offset through the
-//     8-bit offsets of ds_read2 and lanes (rows) never share a bank;
-//   * weights are accumulated as exp2(c2 (ref - D)) with ref the distance
-//     of the zero offset, so the zero-offset term is exactly 1 and the sum
-//     never underflows; if some far better match overflows the sum
-//     (>= 2^100) the workgroup redoes that direction with ref = min D.
+//     d*d) and three separable 3-tap box sums, never the (2d+1)^3 direct sum:
+//     along z in registers, along x by marching over the BX+2 planes with a
+//     two-plane ring, and last along y with two DPP adds across lanes (so the
+//     cross-lane sum runs on the BX output planes only);
+//   * the neighbour phase's weight source u_j and image f_j are staged in LDS
+//     one x-offset (dx) at a time: BX+2 u_j planes and BX f_j planes with the
+//     y/z halo of the window, clamped to the grid (clamp-to-edge); the LDS
+//     layout is [row][plane][z] with an odd row stride, so one base address
+//     per lane serves every plane of a search offset through the 8-bit
+//     offsets of ds_read2, and lanes (rows) never share a bank;
+//   * with HALVES = 2 two sets of waves own the same outputs and split the
+//     (dy, dz) offset pairs of every dx (alternate pairs), sharing the staged
+//     tile; their sums are added in a fixed order;
+//   * weights are accumulated as exp2(c2 (ref - D)) with ref the distance of
+//     the zero offset, so the zero-offset term is exactly 1 and the sum never
+//     underflows; if some far better match overflows the sum (>= 2^100) the
+//     workgroup redoes that direction with ref = min D over the window.
 #include <math.h>
 
 #include <type_traits>
 
 #include "tnlm_internal.h"
 
-#ifndef TNLM_TILE_BX
-#define TNLM_TILE_BX 4  // output x-planes per lane
-#endif
-
 namespace tnlm {
 namespace {
 
 constexpr int kBZ = 4;              // output z per lane
 constexpr int kSegOut = 30;         // output rows per 32-lane segment
-constexpr int kWaves = 4;           // waves per workgroup (one z-block each)
-constexpr int kThreads = 64 * kWaves;
 constexpr int kTY = kSegOut;        // tile extent in y (one segment)
-constexpr int kTZ = 2 * kWaves * kBZ;  // tile extent in z (one z-block per half-wave)
 constexpr float kZOverflow = 1.2676506e30f;  // 2^100
 
-template <int M, int BX>
+// Tile shape: BX output x-planes per lane, ZB z-blocks per tile, HALVES sets
+// of waves splitting the offsets.
+template <int BX_, int ZB_, int HALVES_>
+struct Cfg {
+    static constexpr int BX = BX_, ZB = ZB_, HALVES = HALVES_;
+    static constexpr int WAVES_HALF = ZB / 2;
+    static constexpr int THREADS = 64 * WAVES_HALF * HALVES;
+    static constexpr int TZ = kBZ * ZB;
+};
+// the configuration the library launches
+#ifndef TNLM_FWD_CFG
+#define TNLM_FWD_CFG 4, 8, 1
+#endif
+using CfgSel = Cfg<TNLM_FWD_CFG>;
+
+template <int M, class C>
 struct TG {
-    static constexpr int YL = kTY + 2 + 2 * M;  // LDS rows: y0-1-M .. y0+kTY+M
-    static constexpr int ZL = kTZ + 2 + 2 * M;  // LDS z:    z0-1-M .. z0+kTZ+M
-    static constexpr int UPL = BX + 2;          // u_j planes per dx
-    static constexpr int FPL = BX;              // f_j planes per dx
-    static constexpr int RU = (UPL * ZL) | 1;   // odd row strides: rows never
-    static constexpr int RF = (FPL * ZL) | 1;   // share an LDS bank
+    static constexpr int YL = kTY + 2 + 2 * M;    // LDS rows: y0-1-M .. y0+kTY+M
+    static constexpr int ZL = C::TZ + 2 + 2 * M;  // LDS z:    z0-1-M .. z0+TZ+M
+    static constexpr int UPL = C::BX + 2;         // u_j planes per dx
+    static constexpr int FPL = C::BX;             // f_j planes per dx
+    static constexpr int RU = (UPL * ZL) | 1;     // odd row strides: rows never
+    static constexpr int RF = (FPL * ZL) | 1;     // share an LDS bank
     // offsets from a lane's per-(dy, dz) base: plane xp at xp*ZL, z-slot k
     static_assert((UPL - 1) * ZL + kBZ + 1 < 256,
                   "one ds_read2 base per lane must reach every plane");
@@ -64,7 +75,6 @@ struct TG {
 struct TileGrid {
     int ntx, nty, ntz;
     int nblocks;
-    int tx;  // tile extent in x (= BX)
 };
 
 __device__ __forceinline__ float from_below(float v)  // lane l <- lane l-1
@@ -106,41 +116,49 @@ __device__ __forceinline__ void box_dist(const float (&ui)[BX + 2][kBZ + 2], Loa
             const float d = ui[xp][k] - uj(xp, k);
             sq[k] = d * d;
         }
-        float py[kBZ];
+        float pz[kBZ];
 #pragma unroll
-        for (int k = 0; k < kBZ; ++k) {
-            const float pz = sq[k] + sq[k + 1] + sq[k + 2];
-            py[k] = (from_below(pz) + pz) + from_above(pz);
-        }
+        for (int k = 0; k < kBZ; ++k)
+            pz[k] = sq[k] + sq[k + 1] + sq[k + 2];
         if (xp >= 2) {
 #pragma unroll
-            for (int k = 0; k < kBZ; ++k)
-                out(xp - 2, k, (p0[k] + p1[k]) + py[k]);
+            for (int k = 0; k < kBZ; ++k) {
+                const float pxz = (p0[k] + p1[k]) + pz[k];
+                out(xp - 2, k, (from_below(pxz) + pxz) + from_above(pxz));
+            }
         }
 #pragma unroll
         for (int k = 0; k < kBZ; ++k) {
             p0[k] = p1[k];
-            p1[k] = py[k];
+            p1[k] = pz[k];
         }
     }
 }
 
-template <typename T, int M, int MODE, int BX>
-__global__ void __launch_bounds__(kThreads) fwd_tiled_kernel(Geo g, FwdArgs a, TileGrid tg)
+template <typename T, int M, int MODE, class C>
+__global__ void __launch_bounds__(C::THREADS) fwd_tiled_kernel(Geo g, FwdArgs a, TileGrid tg)
 {
-    using G = TG<M, BX>;
+    using G = TG<M, C>;
+    constexpr int BX = C::BX;
     constexpr int kTX = BX;
-    __shared__ float sU[G::YL * G::RU];
-    __shared__ float sF[(MODE == FWD_WEIGHTS ? 1 : G::YL * G::RF)];
+    constexpr int kTZ = C::TZ;
+    constexpr int S = 2 * M + 1;
+    constexpr int nU = G::YL * G::RU;
+    constexpr int nF = (MODE == FWD_WEIGHTS ? 0 : G::YL * G::RF);
+    // transfer area for the second half's sums: Z and N of every output
+    constexpr int kXfer = (C::HALVES == 2 ? 64 * C::WAVES_HALF * 2 * BX * kBZ : 0);
+    constexpr int kLds = (nU + nF > kXfer ? nU + nF : kXfer);
+    __shared__ float lds[kLds];
     __shared__ int s_redo;
-    __shared__ dfloat s_part[kWaves];
+    __shared__ dfloat s_part[C::WAVES_HALF];
+    float *sU = lds;
+    float *sF = lds + nU;
 
     // ---- tile of this workgroup (blocks of one XCD get consecutive tiles)
     const int b = blockIdx.x;
     const int q8 = tg.nblocks >> 3, r8 = tg.nblocks & 7;
     const int xcd = b & 7;
-    const int tile = xcd * q8 + min(xcd, r8) + (b >> 3);
-    int t = tile;
+    int t = xcd * q8 + min(xcd, r8) + (b >> 3);
     const int tz = t % tg.ntz;
     t /= tg.ntz;
     const int ty = t % tg.nty;
@@ -150,7 +168,9 @@ __global__ void __launch_bounds__(kThreads) fwd_tiled_kernel(Geo g, FwdArgs a, T
     const int x0 = tx * kTX, y0 = ty * kTY, z0 = tz * kTZ;
 
     const int tid = threadIdx.x;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wave = wid % C::WAVES_HALF;  // which pair of z-blocks
+    const int half = wid / C::WAVES_HALF;  // which offset pairs
     const int lane = tid & 63;
     const int seg = lane >> 5, l = lane & 31;
     const int y = y0 - 1 + l;
@@ -165,8 +185,11 @@ __global__ void __launch_bounds__(kThreads) fwd_tiled_kernel(Geo g, FwdArgs a, T
     const int nx = g.nx, ny = g.ny, nz = g.nz;
     const T *u = (const T *)a.u;
     const T *f = (const T *)a.f;
+    // masks are needed where some candidate of some output of this wave
+    // leaves the grid (decided per wave: x and y per workgroup, z per wave)
+    const int zw = z0 + 2 * kBZ * wave;  // the wave's two z-blocks: zw .. zw+7
     const bool border = (x0 - M < 0) || (x0 + kTX - 1 + M >= nx) || (y0 - M < 0) ||
-                        (y0 + kTY - 1 + M >= ny) || (z0 - M < 0) || (z0 + kTZ - 1 + M >= nz);
+                        (y0 + kTY - 1 + M >= ny) || (zw - M < 0) || (zw + 2 * kBZ - 1 + M >= nz);
 
     auto vox = [&](int ph, int xx, int yy, int zz) -> int64_t {
         return (int64_t)ph * N + ((int64_t)xx * ny + yy) * nz + zz;
@@ -209,6 +232,7 @@ __global__ void __launch_bounds__(kThreads) fwd_tiled_kernel(Geo g, FwdArgs a, T
     // one z column, and the (row, plane) pairs are shared out by lane group
     constexpr int kCols = 64;  // lanes per column group (>= ZL)
     static_assert(G::ZL <= kCols, "one z column per lane");
+    constexpr int nGrp = C::THREADS / kCols;
     const int col = tid & (kCols - 1);
     const int grp = tid / kCols;
     const bool col_ok = col < G::ZL;
@@ -216,7 +240,6 @@ __global__ void __launch_bounds__(kThreads) fwd_tiled_kernel(Geo g, FwdArgs a, T
     auto stage = [&](int j, int dx) {
         if (!col_ok)
             return;
-        constexpr int nGrp = kThreads / kCols;
         const T *uj = u + (int64_t)j * N + gzc;
         const T *fj = f + (int64_t)j * N + gzc;
 #pragma unroll 4
@@ -237,51 +260,58 @@ __global__ void __launch_bounds__(kThreads) fwd_tiled_kernel(Geo g, FwdArgs a, T
         }
     };
 
-    // one sweep over the window: PASS_ACC accumulates, PASS_MIN takes min D;
-    // BORD masks candidates outside the grid (tiles near a border)
-    auto sweep = [&](int j, auto pass_c, auto bord_c) {
+    // one sweep over the window (offset pairs p0, p0+step, ... of every dx):
+    // PASS_ACC accumulates, PASS_MIN takes min D; BORD masks candidates
+    // outside the grid. Every wave stages and meets every barrier.
+    auto sweep = [&](int j, auto pass_c, auto bord_c, int p0, int pstep) {
         constexpr int pass = decltype(pass_c)::value;
         constexpr bool bord = decltype(bord_c)::value;
         for (int dx = -M; dx <= M; ++dx) {
             __syncthreads();
             stage(j, dx);
             __syncthreads();
-            for (int dy = -M; dy <= M; ++dy) {
+            for (int pr = p0; pr < S * S; pr += pstep) {
+                const int dy = pr / S - M, dz = pr - (pr / S) * S - M;
                 const bool yval = (unsigned)(y + dy) < (unsigned)ny;
-                const float *rowU = sU + (ry + dy) * G::RU + zoffU;
-                const float *rowF = sF + (ry + dy) * G::RF + zoffF;
-                for (int dz = -M; dz <= M; ++dz) {
-                    const float *bu = rowU + dz;
-                    const float *bf = rowF + dz;
-                    auto uj = [&](int xp, int k) { return bu[xp * G::ZL + k]; };
-                    auto out = [&](int xo, int k, float D) {
-                        bool valid = true;
+                const float *bu = sU + (ry + dy) * G::RU + zoffU + dz;
+                const float *bf = sF + (ry + dy) * G::RF + zoffF + dz;
+                auto uj = [&](int xp, int k) { return bu[xp * G::ZL + k]; };
+                auto out = [&](int xo, int k, float D) {
+                    bool valid = true;
+                    if (bord)
+                        valid = yval & ((unsigned)(x0 + xo + dx) < (unsigned)nx) &
+                                ((unsigned)(zb + k + dz) < (unsigned)nz);
+                    if (pass == PASS_MIN) {
+                        A.N[xo][k] = fminf(A.N[xo][k], valid ? D : INFINITY);
+                    } else {
+                        float tt = fmaf(D, -g.c2, A.cref[xo][k]);
                         if (bord)
-                            valid = yval & ((unsigned)(x0 + xo + dx) < (unsigned)nx) &
-                                    ((unsigned)(zb + k + dz) < (unsigned)nz);
-                        if (pass == PASS_MIN) {
-                            A.N[xo][k] = fminf(A.N[xo][k], valid ? D : INFINITY);
-                        } else {
-                            float tt = fmaf(D, -g.c2, A.cref[xo][k]);
-                            if (bord)
-                                tt = valid ? tt : -INFINITY;
-                            const float e = __builtin_amdgcn_exp2f(tt);
-                            A.Z[xo][k] += e;
-                            if (MODE == FWD_JACOBI || MODE == FWD_EQ6) {
-                                A.N[xo][k] = fmaf(e, bf[xo * G::ZL + k], A.N[xo][k]);
-                            } else if (MODE == FWD_ENERGY) {
-                                const float r = fi[xo][k] - bf[xo * G::ZL + k];
-                                A.N[xo][k] = fmaf(e * r, r, A.N[xo][k]);
-                            }
+                            tt = valid ? tt : -INFINITY;
+                        const float e = __builtin_amdgcn_exp2f(tt);
+                        A.Z[xo][k] += e;
+                        if (MODE == FWD_JACOBI || MODE == FWD_EQ6) {
+                            A.N[xo][k] = fmaf(e, bf[xo * G::ZL + k], A.N[xo][k]);
+                        } else if (MODE == FWD_ENERGY) {
+                            const float r = fi[xo][k] - bf[xo * G::ZL + k];
+                            A.N[xo][k] = fmaf(e * r, r, A.N[xo][k]);
                         }
-                    };
-                    box_dist<BX>(ui, uj, out);
-                }
+                    }
+                };
+                box_dist<BX>(ui, uj, out);
             }
         }
     };
     using acc_c = std::integral_constant<int, PASS_ACC>;
     using min_c = std::integral_constant<int, PASS_MIN>;
+    auto zero_acc = [&]() {
+#pragma unroll
+        for (int xo = 0; xo < BX; ++xo)
+#pragma unroll
+            for (int k = 0; k < kBZ; ++k) {
+                A.Z[xo][k] = 0.f;
+                A.N[xo][k] = 0.f;
+            }
+    };
 
     for (int slot = 0; slot < 2; ++slot) {
         const int j = slot == 0 ? (i + 1 == g.np ? 0 : i + 1) : (i == 0 ? g.np - 1 : i - 1);
@@ -295,41 +325,64 @@ __global__ void __launch_bounds__(kThreads) fwd_tiled_kernel(Geo g, FwdArgs a, T
                     ujb[xp][k] = load_f(u, vox(j, clampi(x0 - 1 + xp, 0, nx - 1), yc,
                                                clampi(zb - 1 + k, 0, nz - 1)));
             box_dist<BX>(ui, [&](int xp, int k) { return ujb[xp][k]; },
-                     [&](int xo, int k, float D) { A.cref[xo][k] = D * g.c2; });
+                         [&](int xo, int k, float D) { A.cref[xo][k] = D * g.c2; });
         }
-#pragma unroll
-        for (int xo = 0; xo < BX; ++xo)
-#pragma unroll
-            for (int k = 0; k < kBZ; ++k) {
-                A.Z[xo][k] = 0.f;
-                A.N[xo][k] = 0.f;
-            }
+        zero_acc();
         if (border)
-            sweep(j, acc_c{}, std::true_type{});
+            sweep(j, acc_c{}, std::true_type{}, half, C::HALVES);
         else
-            sweep(j, acc_c{}, std::false_type{});
+            sweep(j, acc_c{}, std::false_type{}, half, C::HALVES);
 
-        // overflow of the shifted sum: redo this direction relative to min D
-        bool bad = false;
+        if (C::HALVES == 2) {
+            // the second half hands its sums to the first, added in order
+            __syncthreads();
+            float *xz = lds + (wave * 64 + lane) * (2 * BX * kBZ);
+            if (half == 1) {
 #pragma unroll
-        for (int xo = 0; xo < BX; ++xo)
+                for (int xo = 0; xo < BX; ++xo)
 #pragma unroll
-            for (int k = 0; k < kBZ; ++k)
-                bad |= out_ok(xo, k) && !(A.Z[xo][k] < kZOverflow);
-        if (__any(bad))
-            s_redo = 1;
+                    for (int k = 0; k < kBZ; ++k) {
+                        xz[xo * kBZ + k] = A.Z[xo][k];
+                        xz[BX * kBZ + xo * kBZ + k] = A.N[xo][k];
+                    }
+            }
+            __syncthreads();
+            if (half == 0) {
+#pragma unroll
+                for (int xo = 0; xo < BX; ++xo)
+#pragma unroll
+                    for (int k = 0; k < kBZ; ++k) {
+                        A.Z[xo][k] += xz[xo * kBZ + k];
+                        A.N[xo][k] += xz[BX * kBZ + xo * kBZ + k];
+                    }
+            }
+        }
+
+        // overflow of the shifted sum: redo this direction relative to min D,
+        // by the first half alone over every offset
+        if (half == 0) {
+            bool bad = false;
+#pragma unroll
+            for (int xo = 0; xo < BX; ++xo)
+#pragma unroll
+                for (int k = 0; k < kBZ; ++k)
+                    bad |= out_ok(xo, k) && !(A.Z[xo][k] < kZOverflow);
+            if (__any(bad))
+                s_redo = 1;
+        }
         __syncthreads();
         const int redo = s_redo;
         __syncthreads();
         if (tid == 0)
             s_redo = 0;
         if (redo) {
+            const int p0 = half == 0 ? 0 : S * S;  // the second half only stages
 #pragma unroll
             for (int xo = 0; xo < BX; ++xo)
 #pragma unroll
                 for (int k = 0; k < kBZ; ++k)
                     A.N[xo][k] = INFINITY;
-            sweep(j, min_c{}, std::true_type{});
+            sweep(j, min_c{}, std::true_type{}, p0, 1);
 #pragma unroll
             for (int xo = 0; xo < BX; ++xo)
 #pragma unroll
@@ -337,13 +390,14 @@ __global__ void __launch_bounds__(kThreads) fwd_tiled_kernel(Geo g, FwdArgs a, T
                     const float m = A.N[xo][k];
                     // keep NaN inputs NaN; otherwise the exact minimum
                     A.cref[xo][k] = (m == m) ? m * g.c2 : A.cref[xo][k];
-                    A.Z[xo][k] = 0.f;
-                    A.N[xo][k] = 0.f;
                 }
-            sweep(j, acc_c{}, std::true_type{});
+            zero_acc();
+            sweep(j, acc_c{}, std::true_type{}, p0, 1);
         }
+        if (half != 0)
+            continue;
 
-        // per-direction results
+        // per-direction results (first half only)
 #pragma unroll
         for (int xo = 0; xo < BX; ++xo)
 #pragma unroll
@@ -373,7 +427,7 @@ __global__ void __launch_bounds__(kThreads) fwd_tiled_kernel(Geo g, FwdArgs a, T
             }
     }
 
-    if (MODE == FWD_JACOBI || MODE == FWD_EQ6) {
+    if ((MODE == FWD_JACOBI || MODE == FWD_EQ6) && half == 0) {
         const float rr = 1.f / (2.f + a.mu);
 #pragma unroll
         for (int xo = 0; xo < BX; ++xo)
@@ -398,36 +452,34 @@ __global__ void __launch_bounds__(kThreads) fwd_tiled_kernel(Geo g, FwdArgs a, T
             o.lo = __shfl_xor(esum.lo, off);
             esum = (lane & off) ? df_add(o, esum) : df_add(esum, o);
         }
-        if (lane == 0)
+        if (half == 0 && lane == 0)
             s_part[wave] = esum;
         __syncthreads();
         if (tid == 0) {
             dfloat s = s_part[0];
-            for (int w = 1; w < kWaves; ++w)
+            for (int w = 1; w < C::WAVES_HALF; ++w)
                 s = df_add(s, s_part[w]);
             a.partial[blockIdx.x] = s;
         }
     }
 }
 
-constexpr int kBXSel = TNLM_TILE_BX;
-
 template <typename T, int M>
 hipError_t launch_m(const Geo &g, int mode, const FwdArgs &a, const TileGrid &tg, hipStream_t s)
 {
-    constexpr int B = kBXSel;
+    using C = CfgSel;
     switch (mode) {
     case FWD_WEIGHTS:
-        fwd_tiled_kernel<T, M, FWD_WEIGHTS, B><<<tg.nblocks, kThreads, 0, s>>>(g, a, tg);
+        fwd_tiled_kernel<T, M, FWD_WEIGHTS, C><<<tg.nblocks, C::THREADS, 0, s>>>(g, a, tg);
         break;
     case FWD_JACOBI:
-        fwd_tiled_kernel<T, M, FWD_JACOBI, B><<<tg.nblocks, kThreads, 0, s>>>(g, a, tg);
+        fwd_tiled_kernel<T, M, FWD_JACOBI, C><<<tg.nblocks, C::THREADS, 0, s>>>(g, a, tg);
         break;
     case FWD_EQ6:
-        fwd_tiled_kernel<T, M, FWD_EQ6, B><<<tg.nblocks, kThreads, 0, s>>>(g, a, tg);
+        fwd_tiled_kernel<T, M, FWD_EQ6, C><<<tg.nblocks, C::THREADS, 0, s>>>(g, a, tg);
         break;
     default:
-        fwd_tiled_kernel<T, M, FWD_ENERGY, B><<<tg.nblocks, kThreads, 0, s>>>(g, a, tg);
+        fwd_tiled_kernel<T, M, FWD_ENERGY, C><<<tg.nblocks, C::THREADS, 0, s>>>(g, a, tg);
         break;
     }
     return hipGetLastError();
@@ -451,10 +503,9 @@ hipError_t launch_t(const Geo &g, int mode, const FwdArgs &a, const TileGrid &tg
 TileGrid tile_grid(const Geo &g)
 {
     TileGrid tg;
-    tg.tx = kBXSel;
-    tg.ntx = (g.nx + tg.tx - 1) / tg.tx;
+    tg.ntx = (g.nx + CfgSel::BX - 1) / CfgSel::BX;
     tg.nty = (g.ny + kTY - 1) / kTY;
-    tg.ntz = (g.nz + kTZ - 1) / kTZ;
+    tg.ntz = (g.nz + CfgSel::TZ - 1) / CfgSel::TZ;
     tg.nblocks = g.np * tg.ntx * tg.nty * tg.ntz;
     return tg;
 }
@@ -463,13 +514,11 @@ TileGrid tile_grid(const Geo &g)
 
 bool fwd_tiled_supported(const Geo &g, int mode)
 {
+    (void)mode;  // log-normaliser requests only; w goes to the generic path
     if (g.d != 1 || g.M < 1 || g.M > 4)
         return false;
-    if (mode == FWD_WEIGHTS)
-        return true;  // log-normalisers only; the caller routes w requests elsewhere
-    // grid count must fit the launch
-    const int64_t nb = (int64_t)g.np * ((g.nx + kBXSel - 1) / kBXSel) *
-                       ((g.ny + kTY - 1) / kTY) * ((g.nz + kTZ - 1) / kTZ);
+    const int64_t nb = (int64_t)g.np * ((g.nx + CfgSel::BX - 1) / CfgSel::BX) *
+                       ((g.ny + kTY - 1) / kTY) * ((g.nz + CfgSel::TZ - 1) / CfgSel::TZ);
     return nb < (int64_t(1) << 31);
 }
 

@@ -217,7 +217,7 @@ __global__ void __launch_bounds__(kThreads) grad_tiled_kernel(Geo g, GradArgs a,
                         const float *bf = sV[0] + (ry + dy) * G::RV + zoffV + dz;
                         const float *bl = sV[1] + (ry + dy) * G::RV + zoffV + dz;
                         const float *be = sV[2] + (ry + dy) * G::RV + zoffV + dz;
-                        // D on the Gv block
+                        // D on the Gv block: box sums along z, x, then y (DPP)
                         float D[kEX][kEZ];
                         float p0[kEZ], p1[kEZ];
 #pragma unroll
@@ -228,19 +228,19 @@ __global__ void __launch_bounds__(kThreads) grad_tiled_kernel(Geo g, GradArgs a,
                                 const float d = uk[xs][zs] - bu[xs * G::ZL + zs];
                                 sq[zs] = d * d;
                             }
-                            float py[kEZ];
+                            float pz[kEZ];
 #pragma unroll
                             for (int ze = 0; ze < kEZ; ++ze)
-                                py[ze] = ybox(sq[ze] + sq[ze + 1] + sq[ze + 2]);
+                                pz[ze] = sq[ze] + sq[ze + 1] + sq[ze + 2];
                             if (xs >= 2) {
 #pragma unroll
                                 for (int ze = 0; ze < kEZ; ++ze)
-                                    D[xs - 2][ze] = (p0[ze] + p1[ze]) + py[ze];
+                                    D[xs - 2][ze] = ybox((p0[ze] + p1[ze]) + pz[ze]);
                             }
 #pragma unroll
                             for (int ze = 0; ze < kEZ; ++ze) {
                                 p0[ze] = p1[ze];
-                                p1[ze] = py[ze];
+                                p1[ze] = pz[ze];
                             }
                         }
                         // Gv on the block; image part at the grid outputs
@@ -271,18 +271,18 @@ __global__ void __launch_bounds__(kThreads) grad_tiled_kernel(Geo g, GradArgs a,
                                 if (xe >= 1 && xe <= kBX && ze >= 1 && ze <= kBZ)
                                     gi[xe - 1][ze - 1] += wr;
                             }
-                        // box of Gv onto the outputs, times Delta
-                        float gy[kEX][kBZ];
+                        // box of Gv onto the outputs (z, x, then y), times Delta
+                        float gz[kEX][kBZ];
 #pragma unroll
                         for (int xe = 0; xe < kEX; ++xe)
 #pragma unroll
                             for (int zo = 0; zo < kBZ; ++zo)
-                                gy[xe][zo] = ybox(Gv[xe][zo] + Gv[xe][zo + 1] + Gv[xe][zo + 2]);
+                                gz[xe][zo] = Gv[xe][zo] + Gv[xe][zo + 1] + Gv[xe][zo + 2];
 #pragma unroll
                         for (int xo = 0; xo < kBX; ++xo)
 #pragma unroll
                             for (int zo = 0; zo < kBZ; ++zo) {
-                                const float G3 = (gy[xo][zo] + gy[xo + 1][zo]) + gy[xo + 2][zo];
+                                const float G3 = ybox((gz[xo][zo] + gz[xo + 1][zo]) + gz[xo + 2][zo]);
                                 const float Dl = uk[xo + 2][zo + 2] - bu[(xo + 2) * G::ZL + zo + 2];
                                 gw[xo][zo] = fmaf(Dl, G3, gw[xo][zo]);
                             }
