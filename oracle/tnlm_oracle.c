@@ -413,16 +413,81 @@ void tnlmo_grad_exact_scatter(const ogeom *g, const double *u, const double *f,
 /*       sum_p [Dbar_{k,s}(q'-p, delta) + Dbar_{k+s,-s}(q'-p+delta, -delta)]*/
 /* where Dbar vanishes unless both q'-p and q'-p+delta are in the grid.     */
 /* ------------------------------------------------------------------------ */
-static double dbar(const ogeom *g, const double *u, const double *f, int64_t i,
-                   int slot, int64_t x, int64_t y, int64_t z, int64_t ox,
-                   int64_t oy, int64_t oz)
+/* Per-sample cache of per-voxel statistics (log-normaliser, e) for the
+ * phases and voxels one gathered gradient value touches; filled on first use
+ * by local_sums, so every value equals the uncached definition. */
+typedef struct {
+    int64_t ph[3], nph;        /* phases covered */
+    int64_t x0, y0, z0, ex, ey, ez;  /* voxel box covered */
+    double *lse, *e;           /* [nph][2][box] */
+    unsigned char *done;
+} statcache;
+
+static void cache_init(statcache *c, const ogeom *g, int64_t k, int64_t x, int64_t y, int64_t z)
+{
+    int64_t ph[3] = {phase_of(g, k - 1), phase_of(g, k), phase_of(g, k + 1)};
+    c->nph = 0;
+    for (int a = 0; a < 3; ++a) {
+        int dup = 0;
+        for (int b = 0; b < c->nph; ++b)
+            if (c->ph[b] == ph[a])
+                dup = 1;
+        if (!dup)
+            c->ph[c->nph++] = ph[a];
+    }
+    const int64_t R = g->M + 2 * g->d;
+    c->x0 = clampi(x - R, 0, g->nx - 1);
+    c->y0 = clampi(y - R, 0, g->ny - 1);
+    c->z0 = clampi(z - R, 0, g->nz - 1);
+    c->ex = clampi(x + R, 0, g->nx - 1) - c->x0 + 1;
+    c->ey = clampi(y + R, 0, g->ny - 1) - c->y0 + 1;
+    c->ez = clampi(z + R, 0, g->nz - 1) - c->z0 + 1;
+    int64_t n = c->nph * 2 * c->ex * c->ey * c->ez;
+    c->lse = (double *)malloc(sizeof(double) * n);
+    c->e = (double *)malloc(sizeof(double) * n);
+    c->done = (unsigned char *)calloc((size_t)n, 1);
+}
+
+static void cache_free(statcache *c)
+{
+    free(c->lse);
+    free(c->e);
+    free(c->done);
+}
+
+/* lse and e of voxel (i; x,y,z) towards slot, through the cache when the
+ * voxel lies in it (always the case for the gathered gradient). */
+static void cached_stats(statcache *c, const ogeom *g, const double *u, const double *f,
+                         int64_t i, int slot, int64_t x, int64_t y, int64_t z, double *lse,
+                         double *e)
+{
+    int64_t a = -1;
+    for (int64_t b = 0; b < c->nph; ++b)
+        if (c->ph[b] == i)
+            a = b;
+    int64_t lx = x - c->x0, ly = y - c->y0, lz = z - c->z0;
+    if (a < 0 || !c->lse || lx < 0 || lx >= c->ex || ly < 0 || ly >= c->ey || lz < 0 || lz >= c->ez) {
+        local_sums(g, u, f, i, slot, x, y, z, lse, NULL, e);
+        return;
+    }
+    int64_t t = ((a * 2 + slot) * c->ex + lx) * c->ey * c->ez + ly * c->ez + lz;
+    if (!c->done[t]) {
+        local_sums(g, u, f, i, slot, x, y, z, &c->lse[t], NULL, &c->e[t]);
+        c->done[t] = 1;
+    }
+    *lse = c->lse[t];
+    *e = c->e[t];
+}
+
+static double dbar(statcache *c, const ogeom *g, const double *u, const double *f, int64_t i,
+                   int slot, int64_t x, int64_t y, int64_t z, int64_t ox, int64_t oy, int64_t oz)
 {
     /* dE/dD_{i,slot}(v, delta) for v=(x,y,z); zero when not a valid pair */
     if (!inside(g, x, y, z) || !inside(g, x + ox, y + oy, z + oz))
         return 0.0;
     int64_t j = neighbour(g, i, slot);
     double lse, e;
-    local_sums(g, u, f, i, slot, x, y, z, &lse, NULL, &e);
+    cached_stats(c, g, u, f, i, slot, x, y, z, &lse, &e);
     double w = weight(g, u, i, j, x, y, z, ox, oy, oz, lse);
     double r = f[vidx(g, i, x, y, z)] - f[vidx(g, j, x + ox, y + oy, z + oz)];
     return -w * (r * r - e) / (8.0 * g->h * g->h);
@@ -436,6 +501,8 @@ void tnlmo_grad_exact_at(const ogeom *g, const double *u, const double *f,
     for (int64_t k = 0; k < nidx; ++k) {
         int64_t c, x, y, z;
         unflatten(g, idx[k], &c, &x, &y, &z);
+        statcache cache;
+        cache_init(&cache, g, c, x, y, z);
         /* image part */
         if (gf) {
             double acc = 0.0;
@@ -459,8 +526,10 @@ void tnlmo_grad_exact_at(const ogeom *g, const double *u, const double *f,
             }
             gf[k] = acc;
         }
-        if (!gu)
+        if (!gu) {
+            cache_free(&cache);
             continue;
+        }
         /* weight part: loop over padded positions q' with clamp(q') = q */
         double acc = 0.0;
         int64_t lo[3], hi[3], q[3] = {x, y, z}, n[3] = {g->nx, g->ny, g->nz};
@@ -482,8 +551,8 @@ void tnlmo_grad_exact_at(const ogeom *g, const double *u, const double *f,
                                         for (int64_t py = -g->d; py <= g->d; ++py)
                                             for (int64_t pz = -g->d; pz <= g->d; ++pz) {
                                                 int64_t vx = qx - px, vy = qy - py, vz = qz - pz;
-                                                Gs += dbar(g, u, f, c, slot, vx, vy, vz, ox, oy, oz);
-                                                Gs += dbar(g, u, f, j, back, vx + ox, vy + oy, vz + oz, -ox, -oy, -oz);
+                                                Gs += dbar(&cache, g, u, f, c, slot, vx, vy, vz, ox, oy, oz);
+                                                Gs += dbar(&cache, g, u, f, j, back, vx + ox, vy + oy, vz + oz, -ox, -oy, -oz);
                                             }
                                     if (Gs == 0.0)
                                         continue;
@@ -492,6 +561,7 @@ void tnlmo_grad_exact_at(const ogeom *g, const double *u, const double *f,
                                 }
                     }
         gu[k] = acc;
+        cache_free(&cache);
     }
 }
 

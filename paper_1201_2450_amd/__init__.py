@@ -15,9 +15,10 @@ Importing fails if libtnlm.so has not been built: there is no CPU path.
 from . import _lib
 from ._lib import TNLMError
 from .autograd import TNLMEnergy, tnlm_energy
+from . import metrics
 from .drivers import descend, enhance
 from .ops import energy, grad, jacobi_step, n_offsets, weights, workspace_bytes
 
-__all__ = ["TNLMError", "TNLMEnergy", "tnlm_energy", "descend", "enhance",
+__all__ = ["TNLMError", "TNLMEnergy", "tnlm_energy", "descend", "enhance", "metrics",
            "energy", "grad", "jacobi_step", "n_offsets", "weights",
            "workspace_bytes"]
