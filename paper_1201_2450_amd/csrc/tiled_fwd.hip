@@ -14,12 +14,14 @@
 //   * per search offset the patch distance D(v, delta) of every output is
 //     built from per-position squared differences (d = u_i - u_j(. + delta),
 //     d*d) and three separable 3-tap box sums, never the (2d+1)^3 direct sum:
-//     along z in registers, along x by marching over the BX+2 planes with a
-//     two-plane ring, and last along y with two DPP adds across lanes (so the
-//     cross-lane sum runs on the BX output planes only);
+//     along z in registers (squares fused into the adds), along x over the
+//     BX+2 planes, both with the pair sums of neighbouring outputs shared,
+//     and last along y with two DPP adds across lanes (so the cross-lane sum
+//     runs on the BX output planes only);
 //   * the neighbour phase's weight source u_j and image f_j are staged in LDS
 //     one x-offset (dx) at a time: BX+2 u_j planes and BX f_j planes with the
-//     y/z halo of the window, clamped to the grid (clamp-to-edge); the LDS
+//     y/z halo of the window, clamped to the grid (clamp-to-edge); a lane
+//     clamps a (row, z) cell once and copies it from every plane; the LDS
 //     layout is [row][plane][z] with an odd row stride, so one base address
 //     per lane serves every plane of a search offset through the 8-bit
 //     offsets of ds_read2, and lanes (rows) never share a bank;
@@ -104,33 +106,47 @@ struct Acc {
 // Patch distances of this lane's BX x 4 outputs for one offset, given a
 // functor returning u_j at (plane xp, z-slot k), xp in [0,BX+2), k in [0,6).
 // Calls out(xo, k, D) for every output.
+//
+// The 3-tap box sums along z and x share pair sums between neighbouring
+// outputs: outputs 2q and 2q+1 both contain inputs 2q+1 and 2q+2, so one
+// add of that pair serves both (1.5 adds per output instead of 2), and along
+// z the squares fold into the adds as fused multiply-adds. The y box comes
+// last, across lanes. The δ = 0 reference and the sweep both call this
+// function, so their distances agree bit for bit.
 template <int BX, typename LoadJ, typename Out>
 __device__ __forceinline__ void box_dist(const float (&ui)[BX + 2][kBZ + 2], LoadJ uj, Out out)
 {
-    float p0[kBZ], p1[kBZ];
+    static_assert(BX % 2 == 0 && kBZ % 2 == 0, "pair sharing needs even output counts");
+    float pz[BX + 2][kBZ];
+    float pxa[kBZ];
 #pragma unroll
     for (int xp = 0; xp < BX + 2; ++xp) {
-        float sq[kBZ + 2];
+        float dd[kBZ + 2];
 #pragma unroll
-        for (int k = 0; k < kBZ + 2; ++k) {
-            const float d = ui[xp][k] - uj(xp, k);
-            sq[k] = d * d;
+        for (int k = 0; k < kBZ + 2; ++k)
+            dd[k] = ui[xp][k] - uj(xp, k);
+#pragma unroll
+        for (int k = 0; k < kBZ; k += 2) {
+            const float pr = fmaf(dd[k + 1], dd[k + 1], dd[k + 2] * dd[k + 2]);
+            pz[xp][k] = fmaf(dd[k], dd[k], pr);
+            pz[xp][k + 1] = fmaf(dd[k + 3], dd[k + 3], pr);
         }
-        float pz[kBZ];
-#pragma unroll
-        for (int k = 0; k < kBZ; ++k)
-            pz[k] = sq[k] + sq[k + 1] + sq[k + 2];
-        if (xp >= 2) {
+        // x box: output xo sums columns xo, xo+1, xo+2
+        if (xp >= 2 && (xp % 2) == 0) {
+            const int xo = xp - 2;
 #pragma unroll
             for (int k = 0; k < kBZ; ++k) {
-                const float pxz = (p0[k] + p1[k]) + pz[k];
-                out(xp - 2, k, (from_below(pxz) + pxz) + from_above(pxz));
+                pxa[k] = pz[xo + 1][k] + pz[xo + 2][k];
+                const float pxz = pz[xo][k] + pxa[k];
+                out(xo, k, (from_below(pxz) + pxz) + from_above(pxz));
             }
-        }
+        } else if (xp >= 3) {
+            const int xo = xp - 2;
 #pragma unroll
-        for (int k = 0; k < kBZ; ++k) {
-            p0[k] = p1[k];
-            p1[k] = pz[k];
+            for (int k = 0; k < kBZ; ++k) {
+                const float pxz = pxa[k] + pz[xo + 2][k];
+                out(xo, k, (from_below(pxz) + pxz) + from_above(pxz));
+            }
         }
     }
 }
@@ -228,34 +244,37 @@ __global__ void __launch_bounds__(C::THREADS) fwd_tiled_kernel(Geo g, FwdArgs a,
     Acc<BX> A;
 
     // stages the u_j / f_j planes of one dx into LDS (clamped to the grid),
-    // layout [row][plane][z]; lanes run along z (coalesced), each lane keeps
-    // one z column, and the (row, plane) pairs are shared out by lane group
-    constexpr int kCols = 64;  // lanes per column group (>= ZL)
-    static_assert(G::ZL <= kCols, "one z column per lane");
-    constexpr int nGrp = C::THREADS / kCols;
-    const int col = tid & (kCols - 1);
-    const int grp = tid / kCols;
-    const bool col_ok = col < G::ZL;
-    const int gzc = clampi(z0 - 1 - M + col, 0, nz - 1);
+    // layout [row][plane][z]. Each lane takes (row, z) cells, clamps the
+    // cell once and loads it from every plane: the plane offsets are uniform,
+    // so the per-element work is the load and the LDS store.
+    constexpr int kCells = G::YL * G::ZL;
     auto stage = [&](int j, int dx) {
-        if (!col_ok)
-            return;
-        const T *uj = u + (int64_t)j * N + gzc;
-        const T *fj = f + (int64_t)j * N + gzc;
-#pragma unroll 4
-        for (int rp = grp; rp < G::YL * G::UPL; rp += nGrp) {
-            const int r = rp / G::UPL, p = rp - r * G::UPL;
-            const int gx = clampi(x0 - 1 + dx + p, 0, nx - 1);
+        const int64_t plane = (int64_t)ny * nz;
+        const T *ujp[G::UPL];
+        const T *fjp[G::FPL];
+#pragma unroll
+        for (int p = 0; p < G::UPL; ++p)
+            ujp[p] = u + (int64_t)j * N + clampi(x0 - 1 + dx + p, 0, nx - 1) * plane;
+#pragma unroll
+        for (int p = 0; p < G::FPL; ++p)
+            fjp[p] = f + (int64_t)j * N + clampi(x0 + dx + p, 0, nx - 1) * plane;
+#pragma unroll 2
+        for (int c = tid; c < kCells; c += C::THREADS) {
+            const int r = c / G::ZL, zc = c - r * G::ZL;
             const int gy = clampi(y0 - 1 - M + r, 0, ny - 1);
-            sU[r * G::RU + p * G::ZL + col] = load_f(uj, ((int64_t)gx * ny + gy) * nz);
-        }
-        if (MODE != FWD_WEIGHTS) {
-#pragma unroll 4
-            for (int rp = grp; rp < G::YL * G::FPL; rp += nGrp) {
-                const int r = rp / G::FPL, p = rp - r * G::FPL;
-                const int gx = clampi(x0 + dx + p, 0, nx - 1);
-                const int gy = clampi(y0 - 1 - M + r, 0, ny - 1);
-                sF[r * G::RF + p * G::ZL + col] = load_f(fj, ((int64_t)gx * ny + gy) * nz);
+            const int gz = clampi(z0 - 1 - M + zc, 0, nz - 1);
+            // byte offset of the cell within a plane: ny*nz*sizeof(T) < 2^32
+            const unsigned bo = (unsigned)(gy * nz + gz) * (unsigned)sizeof(T);
+            auto at = [bo](const T *pl) { return load_f((const T *)((const char *)pl + bo), 0); };
+            float *su = sU + r * G::RU + zc;
+#pragma unroll
+            for (int p = 0; p < G::UPL; ++p)
+                su[p * G::ZL] = at(ujp[p]);
+            if (MODE != FWD_WEIGHTS) {
+                float *sf = sF + r * G::RF + zc;
+#pragma unroll
+                for (int p = 0; p < G::FPL; ++p)
+                    sf[p * G::ZL] = at(fjp[p]);
             }
         }
     };
@@ -516,6 +535,9 @@ bool fwd_tiled_supported(const Geo &g, int mode)
 {
     (void)mode;  // log-normaliser requests only; w goes to the generic path
     if (g.d != 1 || g.M < 1 || g.M > 4)
+        return false;
+    // staging addresses a cell within an x-plane by a 32-bit byte offset
+    if ((int64_t)g.ny * g.nz * (int64_t)sizeof(float) >= (int64_t(1) << 32))
         return false;
     const int64_t nb = (int64_t)g.np * ((g.nx + CfgSel::BX - 1) / CfgSel::BX) *
                        ((g.ny + kTY - 1) / kTY) * ((g.nz + CfgSel::TZ - 1) / CfgSel::TZ);

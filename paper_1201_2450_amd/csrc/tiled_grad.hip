@@ -25,8 +25,11 @@
 // in a fixed order at the end, so two waves per SIMD run on 124 KB of LDS. Per
 // search offset a lane builds D on its block grown by one voxel in x and z
 // (box sums of squared differences as in the forward kernel), forms Gv there,
-// and box-sums Gv back onto its outputs. The neighbour phase's u_j, f_j and
-// statistics are staged in LDS one dx at a time, clamped to the grid.
+// and box-sums Gv back onto its outputs; the 3-tap box sums along z and x
+// share the pair sums of neighbouring outputs, and the y box runs across
+// lanes with DPP. The neighbour phase's u_j, f_j and statistics are staged in
+// LDS one dx at a time, clamped to the grid; the two statistics of a position
+// sit side by side, so one ds_read2 fetches both.
 #include <math.h>
 
 #include <type_traits>
@@ -38,6 +41,7 @@ namespace {
 
 constexpr int kBX = 2;            // outputs per lane in x
 constexpr int kBZ = 4;            // outputs per lane in z
+static_assert(kBX % 2 == 0 && kBZ % 2 == 0, "pair-shared box sums need even blocks");
 constexpr int kEX = kBX + 2;      // Gv positions per lane in x
 constexpr int kEZ = kBZ + 2;      // Gv positions per lane in z
 constexpr int kSX = kBX + 4;      // squared-difference planes per lane
@@ -53,9 +57,11 @@ template <int M>
 struct GG {
     static constexpr int YL = kTY + 4 + 2 * M;  // rows Y0-2-M .. Y0+kTY+1+M
     static constexpr int ZL = kTZ + 4 + 2 * M;  // z    Z0-2-M .. Z0+kTZ+1+M
-    static constexpr int RU = (kSX * ZL) | 1;   // u_j row: kSX planes
-    static constexpr int RV = (kEX * ZL) | 1;   // f_j / L2 / e2 rows: kEX planes
+    static constexpr int RU = (kSX * ZL) | 1;      // u_j row: kSX planes
+    static constexpr int RV = (kEX * ZL) | 1;      // f_j row: kEX planes
+    static constexpr int RS = (2 * kEX * ZL) | 1;  // (L2, e2) row: pairs, kEX planes
     static_assert((kSX - 1) * ZL + kSZ < 256, "ds_read2 offsets");
+    static_assert(2 * ((kEX - 1) * ZL + kEZ) < 256, "ds_read2 offsets");
 };
 
 struct GradGrid {
@@ -70,7 +76,6 @@ __device__ __forceinline__ float from_above(float v)
 {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, true));
 }
-__device__ __forceinline__ float ybox(float v) { return (from_below(v) + v) + from_above(v); }
 
 __device__ __forceinline__ int clampi(int a, int lo, int hi)
 {
@@ -83,7 +88,8 @@ __global__ void __launch_bounds__(kThreads) grad_tiled_kernel(Geo g, GradArgs a,
 {
     using G = GG<M>;
     __shared__ float sU[G::YL * G::RU];
-    __shared__ float sV[3][G::YL * G::RV];  // f_j, L2 = lse*log2e, e2
+    __shared__ float sF[G::YL * G::RV];  // f_j
+    __shared__ float sS[G::YL * G::RS];  // (-lse*log2e, e2) side by side
 
     const int b = blockIdx.x;
     const int q8 = gg.nblocks >> 3, r8 = gg.nblocks & 7, xcd = b & 7;
@@ -165,7 +171,7 @@ __global__ void __launch_bounds__(kThreads) grad_tiled_kernel(Geo g, GradArgs a,
 #pragma unroll
             for (int ze = 0; ze < kEZ; ++ze) {
                 const int xx = clampi(X0 - 2 + xe, 0, nx - 1), zz = clampi(zb - 2 + ze, 0, nz - 1);
-                L1[xe][ze] = st(k, slot, 0, xx, yc, zz) * kLog2e;
+                L1[xe][ze] = -st(k, slot, 0, xx, yc, zz) * kLog2e;  // negated, log2 units
                 e1[xe][ze] = st(k, slot, 1, xx, yc, zz);
             }
 
@@ -175,35 +181,45 @@ __global__ void __launch_bounds__(kThreads) grad_tiled_kernel(Geo g, GradArgs a,
                 __syncthreads();
                 {
                     // stage u_j (kSX planes from padded X0-2+dx) and f_j, L2, e2
-                    // (kEX planes from padded X0-1+dx), clamped to the grid
-                    constexpr int perU = kSX * G::ZL, perV = kEX * G::ZL;
-                    constexpr int nU = G::YL * perU, nV = G::YL * perV;
-                    for (int e = tid; e < nU + 3 * nV; e += kThreads) {
-                        int arr, ee, pr;
-                        if (e < nU) {
-                            arr = -1;
-                            ee = e;
-                            pr = perU;
-                        } else {
-                            arr = (e - nU) / nV;
-                            ee = e - nU - arr * nV;
-                            pr = perV;
-                        }
-                        const int r = ee / pr, rem = ee - r * pr;
-                        const int p = rem / G::ZL, c = rem - p * G::ZL;
+                    // (kEX planes from padded X0-1+dx), clamped to the grid. A
+                    // lane takes (row, z) cells, clamps each once and loads it
+                    // from every plane through uniform plane bases.
+                    const int64_t plane = (int64_t)ny * nz;
+                    const T *up[kSX];
+                    const T *fp[kEX];
+                    const float *lp[kEX], *ep[kEX];
+#pragma unroll
+                    for (int p = 0; p < kSX; ++p)
+                        up[p] = u + (int64_t)j * N + clampi(X0 - 3 + dx + p, 0, nx - 1) * plane;
+#pragma unroll
+                    for (int p = 0; p < kEX; ++p) {
+                        const int64_t gx = clampi(X0 - 2 + dx + p, 0, nx - 1) * plane;
+                        fp[p] = f + (int64_t)j * N + gx;
+                        lp[p] = a.stats + ((int64_t)j * 2 + back) * 2 * N + gx;
+                        ep[p] = lp[p] + N;
+                    }
+                    constexpr int kCells = G::YL * G::ZL;
+                    for (int c = tid; c < kCells; c += kThreads) {
+                        const int r = c / G::ZL, zc = c - r * G::ZL;
                         const int gy = clampi(Y0 - 3 - M + r, 0, ny - 1);
-                        const int gz = clampi(Z0 - 3 - M + c, 0, nz - 1);
-                        if (arr < 0) {
-                            const int gx = clampi(X0 - 3 + dx + p, 0, nx - 1);
-                            sU[r * G::RU + p * G::ZL + c] = load_f(u, vox(j, gx, gy, gz));
-                        } else {
-                            const int gx = clampi(X0 - 2 + dx + p, 0, nx - 1);
-                            float v;
-                            if (arr == 0)
-                                v = load_f(f, vox(j, gx, gy, gz));
-                            else
-                                v = st(j, back, arr - 1, gx, gy, gz) * (arr == 1 ? kLog2e : 1.f);
-                            sV[arr][r * G::RV + p * G::ZL + c] = v;
+                        const int gz = clampi(Z0 - 3 - M + zc, 0, nz - 1);
+                        // offset of the cell within a plane: ny*nz*4 < 2^32
+                        const unsigned co = (unsigned)(gy * nz + gz);
+                        auto at = [co](const auto *pl) {
+                            using E = std::remove_cv_t<std::remove_reference_t<decltype(*pl)>>;
+                            return load_f((const E *)((const char *)pl + co * (unsigned)sizeof(E)), 0);
+                        };
+                        float *su = sU + r * G::RU + zc;
+#pragma unroll
+                        for (int p = 0; p < kSX; ++p)
+                            su[p * G::ZL] = at(up[p]);
+                        float *sf = sF + r * G::RV + zc;
+                        float *ss = sS + r * G::RS + 2 * zc;
+#pragma unroll
+                        for (int p = 0; p < kEX; ++p) {
+                            sf[p * G::ZL] = at(fp[p]);
+                            ss[2 * p * G::ZL] = -at(lp[p]) * kLog2e;  // negated, log2 units
+                            ss[2 * p * G::ZL + 1] = at(ep[p]);
                         }
                     }
                 }
@@ -214,48 +230,59 @@ __global__ void __launch_bounds__(kThreads) grad_tiled_kernel(Geo g, GradArgs a,
                     const bool yval = yin && (unsigned)(y + dy) < (unsigned)ny;
                     {
                         const float *bu = sU + (ry + dy) * G::RU + zoffU + dz;
-                        const float *bf = sV[0] + (ry + dy) * G::RV + zoffV + dz;
-                        const float *bl = sV[1] + (ry + dy) * G::RV + zoffV + dz;
-                        const float *be = sV[2] + (ry + dy) * G::RV + zoffV + dz;
-                        // D on the Gv block: box sums along z, x, then y (DPP)
+                        const float *bf = sF + (ry + dy) * G::RV + zoffV + dz;
+                        const float *bs = sS + (ry + dy) * G::RS + 2 * (zoffV + dz);
+                        // D on the Gv block: box sums along z, x, then y (DPP);
+                        // neighbouring outputs 2q, 2q+1 share the sum of
+                        // inputs 2q+1 and 2q+2 (squares fused along z)
                         float D[kEX][kEZ];
-                        float p0[kEZ], p1[kEZ];
+                        float pz[kSX][kEZ];
 #pragma unroll
                         for (int xs = 0; xs < kSX; ++xs) {
-                            float sq[kSZ];
+                            float dd[kSZ];
 #pragma unroll
-                            for (int zs = 0; zs < kSZ; ++zs) {
-                                const float d = uk[xs][zs] - bu[xs * G::ZL + zs];
-                                sq[zs] = d * d;
-                            }
-                            float pz[kEZ];
+                            for (int zs = 0; zs < kSZ; ++zs)
+                                dd[zs] = uk[xs][zs] - bu[xs * G::ZL + zs];
 #pragma unroll
-                            for (int ze = 0; ze < kEZ; ++ze)
-                                pz[ze] = sq[ze] + sq[ze + 1] + sq[ze + 2];
-                            if (xs >= 2) {
-#pragma unroll
-                                for (int ze = 0; ze < kEZ; ++ze)
-                                    D[xs - 2][ze] = ybox((p0[ze] + p1[ze]) + pz[ze]);
-                            }
-#pragma unroll
-                            for (int ze = 0; ze < kEZ; ++ze) {
-                                p0[ze] = p1[ze];
-                                p1[ze] = pz[ze];
+                            for (int ze = 0; ze < kEZ; ze += 2) {
+                                const float pr = fmaf(dd[ze + 1], dd[ze + 1], dd[ze + 2] * dd[ze + 2]);
+                                pz[xs][ze] = fmaf(dd[ze], dd[ze], pr);
+                                pz[xs][ze + 1] = fmaf(dd[ze + 3], dd[ze + 3], pr);
                             }
                         }
+#pragma unroll
+                        for (int xe = 0; xe < kEX; xe += 2)
+#pragma unroll
+                            for (int ze = 0; ze < kEZ; ++ze) {
+                                const float pr = pz[xe + 1][ze] + pz[xe + 2][ze];
+                                D[xe][ze] = pz[xe][ze] + pr;
+                                D[xe + 1][ze] = pr + pz[xe + 3][ze];
+                            }
+                        // y box across lanes, all reads of a pass after all writes
+                        // of the previous one (no DPP read-after-write stalls)
+                        float Dy[kEX][kEZ];
+#pragma unroll
+                        for (int xe = 0; xe < kEX; ++xe)
+#pragma unroll
+                            for (int ze = 0; ze < kEZ; ++ze)
+                                Dy[xe][ze] = from_below(D[xe][ze]) + D[xe][ze];
+#pragma unroll
+                        for (int xe = 0; xe < kEX; ++xe)
+#pragma unroll
+                            for (int ze = 0; ze < kEZ; ++ze)
+                                D[xe][ze] = Dy[xe][ze] + from_above(D[xe][ze]);
                         // Gv on the block; image part at the grid outputs
                         float Gv[kEX][kEZ];
 #pragma unroll
                         for (int xe = 0; xe < kEX; ++xe)
 #pragma unroll
                             for (int ze = 0; ze < kEZ; ++ze) {
-                                const float tt = -c2 * D[xe][ze];
                                 const float fj = bf[xe * G::ZL + ze];
-                                const float w1 = __builtin_amdgcn_exp2f(tt - L1[xe][ze]);
-                                const float w2 = __builtin_amdgcn_exp2f(tt - bl[xe * G::ZL + ze]);
+                                const float w1 = __builtin_amdgcn_exp2f(fmaf(D[xe][ze], -c2, L1[xe][ze]));
+                                const float w2 = __builtin_amdgcn_exp2f(fmaf(D[xe][ze], -c2, bs[2 * (xe * G::ZL + ze)]));
                                 const float r = fk[xe][ze] - fj;
                                 const float r2 = r * r;
-                                float gv = fmaf(w2, r2 - be[xe * G::ZL + ze], w1 * (r2 - e1[xe][ze]));
+                                float gv = fmaf(w2, r2 - bs[2 * (xe * G::ZL + ze) + 1], w1 * (r2 - e1[xe][ze]));
                                 float wr = (w1 + w2) * r;
                                 if (bord) {
                                     // v = padded (X0-1+xe, Yp, zb-1+ze) - 1 and v + delta in the grid
@@ -271,18 +298,36 @@ __global__ void __launch_bounds__(kThreads) grad_tiled_kernel(Geo g, GradArgs a,
                                 if (xe >= 1 && xe <= kBX && ze >= 1 && ze <= kBZ)
                                     gi[xe - 1][ze - 1] += wr;
                             }
-                        // box of Gv onto the outputs (z, x, then y), times Delta
+                        // box of Gv onto the outputs (z, x, then y), times Delta,
+                        // with the same pair sharing
                         float gz[kEX][kBZ];
 #pragma unroll
                         for (int xe = 0; xe < kEX; ++xe)
 #pragma unroll
+                            for (int zo = 0; zo < kBZ; zo += 2) {
+                                const float pr = Gv[xe][zo + 1] + Gv[xe][zo + 2];
+                                gz[xe][zo] = Gv[xe][zo] + pr;
+                                gz[xe][zo + 1] = pr + Gv[xe][zo + 3];
+                            }
+                        float gx[kBX][kBZ], gy[kBX][kBZ];
+#pragma unroll
+                        for (int xo = 0; xo < kBX; xo += 2)
+#pragma unroll
+                            for (int zo = 0; zo < kBZ; ++zo) {
+                                const float pr = gz[xo + 1][zo] + gz[xo + 2][zo];
+                                gx[xo][zo] = gz[xo][zo] + pr;
+                                gx[xo + 1][zo] = pr + gz[xo + 3][zo];
+                            }
+#pragma unroll
+                        for (int xo = 0; xo < kBX; ++xo)
+#pragma unroll
                             for (int zo = 0; zo < kBZ; ++zo)
-                                gz[xe][zo] = Gv[xe][zo] + Gv[xe][zo + 1] + Gv[xe][zo + 2];
+                                gy[xo][zo] = from_below(gx[xo][zo]) + gx[xo][zo];
 #pragma unroll
                         for (int xo = 0; xo < kBX; ++xo)
 #pragma unroll
                             for (int zo = 0; zo < kBZ; ++zo) {
-                                const float G3 = ybox((gz[xo][zo] + gz[xo + 1][zo]) + gz[xo + 2][zo]);
+                                const float G3 = gy[xo][zo] + from_above(gx[xo][zo]);
                                 const float Dl = uk[xo + 2][zo + 2] - bu[(xo + 2) * G::ZL + zo + 2];
                                 gw[xo][zo] = fmaf(Dl, G3, gw[xo][zo]);
                             }
@@ -401,6 +446,9 @@ GradGrid grad_grid(const Geo &g)
 bool grad_tiled_supported(const Geo &g)
 {
     if (g.d != 1 || g.M < 1 || g.M > 4)
+        return false;
+    // staging addresses a cell within an x-plane by a 32-bit byte offset
+    if ((int64_t)g.ny * g.nz * (int64_t)sizeof(float) >= (int64_t(1) << 32))
         return false;
     const int64_t nb = (int64_t)g.np * ((g.nx + 2 + kBX - 1) / kBX) *
                        ((g.ny + 2 + kTY - 1) / kTY) * ((g.nz + 2 + kTZ - 1) / kTZ);
