@@ -292,8 +292,8 @@ __global__ void __launch_bounds__(C::THREADS) fwd_tiled_kernel(Geo g, FwdArgs a,
             for (int pr = p0; pr < S * S; pr += pstep) {
                 const int dy = pr / S - M, dz = pr - (pr / S) * S - M;
                 const bool yval = (unsigned)(y + dy) < (unsigned)ny;
-                const float *bu = sU + (ry + dy) * G::RU + zoffU + dz;
-                const float *bf = sF + (ry + dy) * G::RF + zoffF + dz;
+                lds_float *bu = lds_base(sU + (ry + dy) * G::RU + zoffU + dz);
+                lds_float *bf = lds_base(sF + (ry + dy) * G::RF + zoffF + dz);
                 auto uj = [&](int xp, int k) { return bu[xp * G::ZL + k]; };
                 auto out = [&](int xo, int k, float D) {
                     bool valid = true;

@@ -82,13 +82,15 @@ __device__ __forceinline__ int clampi(int a, int lo, int hi)
     return a < lo ? lo : (a > hi ? hi : a);
 }
 
-template <typename T, int M>
+// SAME: the image is the weight source (f and u are one volume), so f_j is
+// the staged u_j and the residual r is the centre squared-difference term.
+template <typename T, int M, bool SAME>
 __global__ void __launch_bounds__(kThreads) grad_tiled_kernel(Geo g, GradArgs a, float *gpad,
                                                               GradGrid gg)
 {
     using G = GG<M>;
     __shared__ float sU[G::YL * G::RU];
-    __shared__ float sF[G::YL * G::RV];  // f_j
+    __shared__ float sF[SAME ? 1 : G::YL * G::RV];  // f_j (u_j when SAME)
     __shared__ float sS[G::YL * G::RS];  // (-lse*log2e, e2) side by side
 
     const int b = blockIdx.x;
@@ -138,13 +140,15 @@ __global__ void __launch_bounds__(kThreads) grad_tiled_kernel(Geo g, GradArgs a,
             uk[xs][zs] = load_f(u, vox(k, clampi(X0 - 3 + xs, 0, nx - 1), yc,
                                        clampi(zb - 3 + zs, 0, nz - 1)));
     // f_k on the Gv block (padded X0-1 .. X0+kBX, zb-1 .. zb+kBZ)
-    float fk[kEX][kEZ];
+    float fk[SAME ? 1 : kEX][SAME ? 1 : kEZ];
+    if (!SAME) {
 #pragma unroll
-    for (int xe = 0; xe < kEX; ++xe)
+        for (int xe = 0; xe < kEX; ++xe)
 #pragma unroll
-        for (int ze = 0; ze < kEZ; ++ze)
-            fk[xe][ze] = load_f(f, vox(k, clampi(X0 - 2 + xe, 0, nx - 1), yc,
-                                       clampi(zb - 2 + ze, 0, nz - 1)));
+            for (int ze = 0; ze < kEZ; ++ze)
+                fk[xe][ze] = load_f(f, vox(k, clampi(X0 - 2 + xe, 0, nx - 1), yc,
+                                           clampi(zb - 2 + ze, 0, nz - 1)));
+    }
 
     float gw[kBX][kBZ], gi[kBX][kBZ];
 #pragma unroll
@@ -217,7 +221,8 @@ __global__ void __launch_bounds__(kThreads) grad_tiled_kernel(Geo g, GradArgs a,
                         float *ss = sS + r * G::RS + 2 * zc;
 #pragma unroll
                         for (int p = 0; p < kEX; ++p) {
-                            sf[p * G::ZL] = at(fp[p]);
+                            if (!SAME)
+                                sf[p * G::ZL] = at(fp[p]);
                             ss[2 * p * G::ZL] = -at(lp[p]) * kLog2e;  // negated, log2 units
                             ss[2 * p * G::ZL + 1] = at(ep[p]);
                         }
@@ -229,20 +234,26 @@ __global__ void __launch_bounds__(kThreads) grad_tiled_kernel(Geo g, GradArgs a,
                     const int dy = pr / S - M, dz = pr - (pr / S) * S - M;
                     const bool yval = yin && (unsigned)(y + dy) < (unsigned)ny;
                     {
-                        const float *bu = sU + (ry + dy) * G::RU + zoffU + dz;
-                        const float *bf = sF + (ry + dy) * G::RV + zoffV + dz;
-                        const float *bs = sS + (ry + dy) * G::RS + 2 * (zoffV + dz);
+                        lds_float *bu = lds_base(sU + (ry + dy) * G::RU + zoffU + dz);
+                        lds_float *bf = lds_base(SAME ? sU : sF + (ry + dy) * G::RV + zoffV + dz);
+                        lds_float *bs = lds_base(sS + (ry + dy) * G::RS + 2 * (zoffV + dz));
                         // D on the Gv block: box sums along z, x, then y (DPP);
                         // neighbouring outputs 2q, 2q+1 share the sum of
                         // inputs 2q+1 and 2q+2 (squares fused along z)
                         float D[kEX][kEZ];
                         float pz[kSX][kEZ];
+                        float rc[SAME ? kEX : 1][SAME ? kEZ : 1];  // u_k - u_j on the Gv block
 #pragma unroll
                         for (int xs = 0; xs < kSX; ++xs) {
                             float dd[kSZ];
 #pragma unroll
                             for (int zs = 0; zs < kSZ; ++zs)
                                 dd[zs] = uk[xs][zs] - bu[xs * G::ZL + zs];
+                            if (SAME && xs >= 1 && xs <= kEX) {
+#pragma unroll
+                                for (int ze = 0; ze < kEZ; ++ze)
+                                    rc[xs - 1][ze] = dd[ze + 1];
+                            }
 #pragma unroll
                             for (int ze = 0; ze < kEZ; ze += 2) {
                                 const float pr = fmaf(dd[ze + 1], dd[ze + 1], dd[ze + 2] * dd[ze + 2]);
@@ -277,10 +288,9 @@ __global__ void __launch_bounds__(kThreads) grad_tiled_kernel(Geo g, GradArgs a,
                         for (int xe = 0; xe < kEX; ++xe)
 #pragma unroll
                             for (int ze = 0; ze < kEZ; ++ze) {
-                                const float fj = bf[xe * G::ZL + ze];
                                 const float w1 = __builtin_amdgcn_exp2f(fmaf(D[xe][ze], -c2, L1[xe][ze]));
                                 const float w2 = __builtin_amdgcn_exp2f(fmaf(D[xe][ze], -c2, bs[2 * (xe * G::ZL + ze)]));
-                                const float r = fk[xe][ze] - fj;
+                                const float r = SAME ? rc[xe][ze] : fk[xe][ze] - bf[xe * G::ZL + ze];
                                 const float r2 = r * r;
                                 float gv = fmaf(w2, r2 - bs[2 * (xe * G::ZL + ze) + 1], w1 * (r2 - e1[xe][ze]));
                                 float wr = (w1 + w2) * r;
@@ -411,23 +421,32 @@ __global__ void __launch_bounds__(256) fold_kernel(Geo g, const float *gpad, flo
     }
 }
 
-template <typename T>
-hipError_t launch_t(const Geo &g, const GradArgs &a, float *gpad, const GradGrid &gg, hipStream_t s)
+template <typename T, bool SAME>
+void launch_m(const Geo &g, const GradArgs &a, float *gpad, const GradGrid &gg, hipStream_t s)
 {
     switch (g.M) {
     case 1:
-        grad_tiled_kernel<T, 1><<<gg.nblocks, kThreads, 0, s>>>(g, a, gpad, gg);
+        grad_tiled_kernel<T, 1, SAME><<<gg.nblocks, kThreads, 0, s>>>(g, a, gpad, gg);
         break;
     case 2:
-        grad_tiled_kernel<T, 2><<<gg.nblocks, kThreads, 0, s>>>(g, a, gpad, gg);
+        grad_tiled_kernel<T, 2, SAME><<<gg.nblocks, kThreads, 0, s>>>(g, a, gpad, gg);
         break;
     case 3:
-        grad_tiled_kernel<T, 3><<<gg.nblocks, kThreads, 0, s>>>(g, a, gpad, gg);
+        grad_tiled_kernel<T, 3, SAME><<<gg.nblocks, kThreads, 0, s>>>(g, a, gpad, gg);
         break;
     default:
-        grad_tiled_kernel<T, 4><<<gg.nblocks, kThreads, 0, s>>>(g, a, gpad, gg);
+        grad_tiled_kernel<T, 4, SAME><<<gg.nblocks, kThreads, 0, s>>>(g, a, gpad, gg);
         break;
     }
+}
+
+template <typename T>
+hipError_t launch_t(const Geo &g, const GradArgs &a, float *gpad, const GradGrid &gg, hipStream_t s)
+{
+    if (a.u == a.f)
+        launch_m<T, true>(g, a, gpad, gg, s);
+    else
+        launch_m<T, false>(g, a, gpad, gg, s);
     return hipGetLastError();
 }
 

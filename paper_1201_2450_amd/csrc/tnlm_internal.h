@@ -34,6 +34,18 @@ __device__ __forceinline__ float load_f(const bf16_t *p, int64_t i)
 }
 __device__ __forceinline__ float load_f(const _Float16 *p, int64_t i) { return (float)p[i]; }
 
+// An LDS pointer whose address the compiler treats as an unknown register
+// value: reads through it use that one register plus small immediate
+// offsets (ds_read2 reaches 255 dwords), instead of folding the array's
+// absolute LDS address into every read and overflowing the offset field.
+using lds_float = __attribute__((address_space(3))) const float;
+__device__ __forceinline__ lds_float *lds_base(const float *p)
+{
+    unsigned a = (unsigned)(size_t)(lds_float *)p;
+    asm("" : "+v"(a));
+    return (lds_float *)(size_t)a;
+}
+
 __device__ __forceinline__ void store_f(float *p, int64_t i, float v) { p[i] = v; }
 __device__ __forceinline__ void store_f(bf16_t *p, int64_t i, float v)
 {
