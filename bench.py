@@ -70,16 +70,18 @@ def cpu_baseline(w, target_s):
     g64 = workload_inputs(w, out_dtype=np.float32)[0].astype(np.float64)
     rng = np.random.default_rng(7)
     total = g64.size
-    n = 256
-    idx = rng.choice(total, size=n, replace=False)
-    t0 = time.perf_counter()
-    oracle.jacobi(g64, g64, g64, w.mu, w.d, w.M, w.h, idx=idx)
-    dt = time.perf_counter() - t0
-    n2 = int(max(256, min(total, n * max(1.0, target_s / max(dt, 1e-3)))))
-    idx = rng.choice(total, size=n2, replace=False)
-    t0 = time.perf_counter()
-    oracle.jacobi(g64, g64, g64, w.mu, w.d, w.M, w.h, idx=idx)
-    dt = time.perf_counter() - t0
+    # batches of random voxels until target_s of oracle time has been spent,
+    # each batch sized from the rate so far (at most ~5 s)
+    n_all, t_all, n = 0, 0.0, 4096
+    while t_all < target_s:
+        idx = rng.choice(total, size=n, replace=False)
+        t0 = time.perf_counter()
+        oracle.jacobi(g64, g64, g64, w.mu, w.d, w.M, w.h, idx=idx)
+        t_all += time.perf_counter() - t0
+        n_all += n
+        rate = n_all / t_all
+        n = int(min(total, max(4096, rate * min(max(target_s - t_all, 0.0), 5.0))))
+    n2, dt = n_all, t_all
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": n2 / dt, "unit": "voxel-updates/s", "cores": threads,
             "kind": "oracle",

@@ -48,7 +48,11 @@ constexpr int kSX = kBX + 4;      // squared-difference planes per lane
 constexpr int kSZ = kBZ + 4;      // squared-difference z per lane
 constexpr int kSegOut = 28;       // outputs per 32-lane segment
 constexpr int kWaves = 4;             // z-blocks per workgroup
-constexpr int kThreads = 2 * 64 * kWaves;  // two waves per z-block
+#ifndef TNLM_GRAD_SETS
+#define TNLM_GRAD_SETS 2
+#endif
+constexpr int kSets = TNLM_GRAD_SETS;  // waves per z-block, splitting the offset pairs
+constexpr int kThreads = kSets * 64 * kWaves;
 constexpr int kTY = 2 * kSegOut;  // 56
 constexpr int kTZ = kWaves * kBZ; // 16
 constexpr float kLog2e = 1.4426950408889634f;
@@ -108,7 +112,7 @@ __global__ void __launch_bounds__(kThreads) grad_tiled_kernel(Geo g, GradArgs a,
     const int tid = threadIdx.x;
     const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wave = wid & (kWaves - 1);  // z-block
-    const int half = wid / kWaves;        // which (dy, dz) pairs this wave takes
+    const int half = wid / kWaves;        // which (dy, dz) pairs this wave takes (set)
     const int lane = tid & 63, seg = lane >> 5, l = lane & 31;
     const int nx = g.nx, ny = g.ny, nz = g.nz;
     const int64_t N = g.N;
@@ -159,10 +163,11 @@ __global__ void __launch_bounds__(kThreads) grad_tiled_kernel(Geo g, GradArgs a,
             gi[xo][zo] = 0.f;
         }
 
-    // tiles whose every Gv position v (lanes 1..30) has v and v+delta in the
-    // grid for all offsets skip the masks (uniform over the workgroup)
+    // waves whose every Gv position v has v and v+delta in the grid for all
+    // offsets skip the masks: x and y decided per workgroup, z per wave (its
+    // z-block), uniform over the wave; both sweeps meet the same barriers
     const bool border = (X0 - 2 - M < 1) || (X0 + kBX + 1 + M > nx) || (Y0 - 2 - M < 1) ||
-                        (Y0 + kTY + 1 + M > ny) || (Z0 - 2 - M < 1) || (Z0 + kTZ + 1 + M > nz);
+                        (Y0 + kTY + 1 + M > ny) || (zb - 2 - M < 1) || (zb + kBZ + 1 + M > nz);
     const float c2 = g.c2;
 
     for (int slot = 0; slot < 2; ++slot) {
@@ -230,7 +235,7 @@ __global__ void __launch_bounds__(kThreads) grad_tiled_kernel(Geo g, GradArgs a,
                 }
                 __syncthreads();
                 constexpr int S = 2 * M + 1;
-                for (int pr = half; pr < S * S; pr += 2) {
+                for (int pr = half; pr < S * S; pr += kSets) {
                     const int dy = pr / S - M, dz = pr - (pr / S) * S - M;
                     const bool yval = yin && (unsigned)(y + dy) < (unsigned)ny;
                     {
@@ -351,32 +356,35 @@ __global__ void __launch_bounds__(kThreads) grad_tiled_kernel(Geo g, GradArgs a,
             sweep(std::false_type{});
     }
 
-    // combine the two halves in a fixed order: the second wave of each pair
-    // hands its sums over through LDS, the first adds and writes
+    // combine the sets in a fixed order: sets 1.. hand their sums over
+    // through LDS, set 0 adds them in set order and writes
     __syncthreads();
     float *xfer = sU;  // the staging tile is free now
     constexpr int kPer = 2 * kBX * kBZ;
-    static_assert(kThreads / 2 * kPer <= GG<M>::YL * GG<M>::RU, "transfer fits");
-    const int slotx = (wave * 64 + lane) * kPer;
-    if (half == 1) {
+    static_assert((kSets - 1) * kWaves * 64 * kPer <= GG<M>::YL * GG<M>::RU, "transfer fits");
+    if (half > 0) {
+        float *xs = xfer + (((half - 1) * kWaves + wave) * 64 + lane) * kPer;
 #pragma unroll
         for (int xo = 0; xo < kBX; ++xo)
 #pragma unroll
             for (int zo = 0; zo < kBZ; ++zo) {
-                xfer[slotx + xo * kBZ + zo] = gw[xo][zo];
-                xfer[slotx + kBX * kBZ + xo * kBZ + zo] = gi[xo][zo];
+                xs[xo * kBZ + zo] = gw[xo][zo];
+                xs[kBX * kBZ + xo * kBZ + zo] = gi[xo][zo];
             }
     }
     __syncthreads();
-    if (half == 1)
+    if (half > 0)
         return;
+    for (int h = 1; h < kSets; ++h) {
+        const float *xs = xfer + (((h - 1) * kWaves + wave) * 64 + lane) * kPer;
 #pragma unroll
-    for (int xo = 0; xo < kBX; ++xo)
+        for (int xo = 0; xo < kBX; ++xo)
 #pragma unroll
-        for (int zo = 0; zo < kBZ; ++zo) {
-            gw[xo][zo] += xfer[slotx + xo * kBZ + zo];
-            gi[xo][zo] += xfer[slotx + kBX * kBZ + xo * kBZ + zo];
-        }
+            for (int zo = 0; zo < kBZ; ++zo) {
+                gw[xo][zo] += xs[xo * kBZ + zo];
+                gi[xo][zo] += xs[kBX * kBZ + xo * kBZ + zo];
+            }
+    }
 
     // write: weight part to the padded buffer, image part to grad_f
     const float sw = -0.5f * g.inv2h2;  // 2 * (-1/(8h^2))
