@@ -245,6 +245,21 @@ __global__ void __launch_bounds__(kThreads) grad_tiled_kernel(Geo g, GradArgs a,
                         // D on the Gv block: box sums along z, x, then y (DPP);
                         // neighbouring outputs 2q, 2q+1 share the sum of
                         // inputs 2q+1 and 2q+2 (squares fused along z)
+                        //
+                        // When u = f each phase first reads all its LDS operands
+                        // into registers behind a scheduling fence, so the reads
+                        // are in flight together; left alone, the scheduler
+                        // issues one read, waits for it and issues the next. (The
+                        // u != f instance holds f_k too and has no registers to
+                        // spare for the batches.)
+                        float ub[kSX][kSZ];
+#pragma unroll
+                        for (int xs = 0; xs < kSX; ++xs)
+#pragma unroll
+                            for (int zs = 0; zs < kSZ; ++zs)
+                                ub[xs][zs] = bu[xs * G::ZL + zs];
+                        if (SAME)
+                            __builtin_amdgcn_sched_barrier(0);
                         float D[kEX][kEZ];
                         float pz[kSX][kEZ];
                         float rc[SAME ? kEX : 1][SAME ? kEZ : 1];  // u_k - u_j on the Gv block
@@ -253,7 +268,7 @@ __global__ void __launch_bounds__(kThreads) grad_tiled_kernel(Geo g, GradArgs a,
                             float dd[kSZ];
 #pragma unroll
                             for (int zs = 0; zs < kSZ; ++zs)
-                                dd[zs] = uk[xs][zs] - bu[xs * G::ZL + zs];
+                                dd[zs] = uk[xs][zs] - ub[xs][zs];
                             if (SAME && xs >= 1 && xs <= kEX) {
 #pragma unroll
                                 for (int ze = 0; ze < kEZ; ++ze)
@@ -288,16 +303,26 @@ __global__ void __launch_bounds__(kThreads) grad_tiled_kernel(Geo g, GradArgs a,
                             for (int ze = 0; ze < kEZ; ++ze)
                                 D[xe][ze] = Dy[xe][ze] + from_above(D[xe][ze]);
                         // Gv on the block; image part at the grid outputs
+                        float sl[kEX][kEZ], se[kEX][kEZ];
+#pragma unroll
+                        for (int xe = 0; xe < kEX; ++xe)
+#pragma unroll
+                            for (int ze = 0; ze < kEZ; ++ze) {
+                                sl[xe][ze] = bs[2 * (xe * G::ZL + ze)];
+                                se[xe][ze] = bs[2 * (xe * G::ZL + ze) + 1];
+                            }
+                        if (SAME)
+                            __builtin_amdgcn_sched_barrier(0);
                         float Gv[kEX][kEZ];
 #pragma unroll
                         for (int xe = 0; xe < kEX; ++xe)
 #pragma unroll
                             for (int ze = 0; ze < kEZ; ++ze) {
                                 const float w1 = __builtin_amdgcn_exp2f(fmaf(D[xe][ze], -c2, L1[xe][ze]));
-                                const float w2 = __builtin_amdgcn_exp2f(fmaf(D[xe][ze], -c2, bs[2 * (xe * G::ZL + ze)]));
+                                const float w2 = __builtin_amdgcn_exp2f(fmaf(D[xe][ze], -c2, sl[xe][ze]));
                                 const float r = SAME ? rc[xe][ze] : fk[xe][ze] - bf[xe * G::ZL + ze];
                                 const float r2 = r * r;
-                                float gv = fmaf(w2, r2 - bs[2 * (xe * G::ZL + ze) + 1], w1 * (r2 - e1[xe][ze]));
+                                float gv = fmaf(w2, r2 - se[xe][ze], w1 * (r2 - e1[xe][ze]));
                                 float wr = (w1 + w2) * r;
                                 if (bord) {
                                     // v = padded (X0-1+xe, Yp, zb-1+ze) - 1 and v + delta in the grid
@@ -343,7 +368,9 @@ __global__ void __launch_bounds__(kThreads) grad_tiled_kernel(Geo g, GradArgs a,
 #pragma unroll
                             for (int zo = 0; zo < kBZ; ++zo) {
                                 const float G3 = gy[xo][zo] + from_above(gx[xo][zo]);
-                                const float Dl = uk[xo + 2][zo + 2] - bu[(xo + 2) * G::ZL + zo + 2];
+                                // Delta at the output (the centre difference when u = f)
+                                const float Dl = SAME ? rc[xo + 1][zo + 1]
+                                                      : uk[xo + 2][zo + 2] - bu[(xo + 2) * G::ZL + zo + 2];
                                 gw[xo][zo] = fmaf(Dl, G3, gw[xo][zo]);
                             }
                     }
