@@ -14,8 +14,9 @@ import torch
 
 import paper_1201_2450_amd as tnlm
 from oracle import oracle
+from tests.test_gpu_workloads import sample_idx
 from tests.gpu_util import (FP32_TOL, STORE_EPS, assert_close, device, host,
-                            inputs, say, to_dev, tol_for)
+                            inputs, say, to_dev, tol_for, with_peaks)
 
 pytestmark = pytest.mark.gpu
 
@@ -133,6 +134,29 @@ def test_results_are_bitwise_deterministic():
         outs.append([t.cpu().numpy().copy() for t in (j, e, st, gt)])
     for a, b in zip(*outs):
         assert np.array_equal(a.view(np.uint8), b.view(np.uint8))
+
+
+@pytest.mark.parametrize("M", [1, 2, 3, 4])
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_adjoint_image_equal_to_weight_source_instance(M, storage):
+    """The adjoint has an instance for u and f being one buffer (f_j read
+    from the staged u_j, residual from the centre difference). Handing it a
+    copy of f as u takes the general instance; on interior and border tiles
+    both must give the same gradient, and both match the oracle. The grid
+    holds interior (unmasked) tiles for every M."""
+    shape, d, h = (2, 16, 120, 30), 1, 0.05
+    say(f"adjoint u=f instance M={M} {storage} {shape}")
+    f64, f = to_dev(inputs(shape, "phantom", 40 + M), storage)
+    u = f.clone()
+    gs_f, gs_u = tnlm.grad(f, d=d, M=M, h=h, mode="exact")           # u is f
+    gg_f, gg_u = tnlm.grad(f, u=u, d=d, M=M, h=h, mode="exact")      # u a copy
+    torch.cuda.synchronize()
+    assert_close(host(gs_f), host(gg_f), FP32_TOL, "dE/df: u = f vs copy")
+    assert_close(host(gs_u), host(gg_u), FP32_TOL, "dE/du: u = f vs copy")
+    idx = with_peaks(sample_idx(shape, 60, M), gs_f, gs_u)
+    rf, ru = oracle.grad_exact_at(f64, f64, d, M, h, idx)
+    assert_close(host(gs_f).ravel()[idx], rf, FP32_TOL, "dE/df vs oracle")
+    assert_close(host(gs_u).ravel()[idx], ru, FP32_TOL, "dE/du vs oracle")
 
 
 def test_constant_volume_is_a_fixed_point_on_gpu():

@@ -18,7 +18,7 @@ import paper_1201_2450_amd as tnlm
 from oracle import oracle
 from phantom import WORKLOADS, quantise, workload_inputs
 from tests.gpu_util import (FP32_TOL, STORE_EPS, assert_close, device, host,
-                            inputs, normwise, say, to_dev)
+                            inputs, normwise, say, to_dev, with_peaks)
 from tests.test_gpu_workloads import sample_idx
 
 pytestmark = pytest.mark.gpu
@@ -68,14 +68,16 @@ def test_storage_error_tables(storage):
     e, st = tnlm.energy(xq, d=d, M=M, h=h, want_stats=True)
     gt = tnlm.grad(xq, d=d, M=M, h=h, mode="exact", stats=st, total=True)
     torch.cuda.synchronize()
+    gidx = with_peaks(idx[:40], gt)
+    idx = with_peaks(idx, out)
     got = {"jacobi": host(out).ravel()[idx],
            "lse": host(lse)[idx // N, :, idx % N],
-           "grad": host(gt).ravel()[idx[:40]]}
+           "grad": host(gt).ravel()[gidx]}
     E = float(e[0]) + float(e[1])
     for name, src in (("kernel", xq64), ("end-to-end", x32_64)):
         ref = {"jacobi": oracle.jacobi(src, src, src, mu, d, M, h, idx=idx),
                "lse": oracle.stats(src, src, d, M, h, idx=idx)[:, :, 0]}
-        rf, ru = oracle.grad_exact_at(src, src, d, M, h, idx[:40])
+        rf, ru = oracle.grad_exact_at(src, src, d, M, h, gidx)
         ref["grad"] = rf + ru
         Er = oracle.energy(src, src, d, M, h)
         errs = {k: normwise(got[k], ref[k]) for k in got}
@@ -102,7 +104,7 @@ def test_fbs512_fp16_gradient_sampled():
     f = torch.from_numpy(f16).to(device())
     gt = tnlm.grad(f, d=w.d, M=w.M, h=w.h, mode="exact", total=True)
     torch.cuda.synchronize()
-    idx = sample_idx(w.shape, 8, 10)
+    idx = with_peaks(sample_idx(w.shape, 8, 10), gt)
     f64 = f16.astype(np.float64)
     rf, ru = oracle.grad_exact_at(f64, f64, w.d, w.M, w.h, idx)
     g32 = gt.cpu().numpy().ravel()[idx]

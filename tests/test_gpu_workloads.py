@@ -13,7 +13,8 @@ import torch
 import paper_1201_2450_amd as tnlm
 from oracle import oracle
 from phantom import WORKLOADS, quantise, workload_inputs
-from tests.gpu_util import FP32_TOL, assert_close, device, host, inputs, say, to_dev
+from tests.gpu_util import (FP32_TOL, assert_close, device, host, inputs, say, to_dev,
+                            with_peaks)
 
 pytestmark = pytest.mark.gpu
 
@@ -65,7 +66,7 @@ def test_interior_tiles_exact_gradient_sampled():
     f64, f = to_dev(inputs(shape, "phantom", 25))
     gf, gu = tnlm.grad(f, u=u, d=d, M=M, h=h, mode="exact")
     torch.cuda.synchronize()
-    idx = sample_idx(shape, 160, 3)
+    idx = with_peaks(sample_idx(shape, 160, 3), gf, gu)
     rf, ru = oracle.grad_exact_at(u64, f64, d, M, h, idx)
     assert_close(host(gf).ravel()[idx], rf, FP32_TOL, "dE/df (sampled)")
     assert_close(host(gu).ravel()[idx], ru, FP32_TOL, "dE/du (sampled)")
@@ -80,7 +81,7 @@ def test_enh256_jacobi_step_sampled():
     g = torch.from_numpy(g32).to(device())
     out = tnlm.jacobi_step(g, g, g, w.mu, d=w.d, M=w.M, h=w.h)
     torch.cuda.synchronize()
-    idx = sample_idx(w.shape, 400, 4)
+    idx = with_peaks(sample_idx(w.shape, 400, 4), out)
     g64 = g32.astype(np.float64)
     ref = oracle.jacobi(g64, g64, g64, w.mu, w.d, w.M, w.h, idx=idx)
     assert_close(host(out).ravel()[idx], ref, FP32_TOL, "f_out (sampled)")
@@ -100,7 +101,7 @@ def test_enh256_storage_jacobi_sampled(storage):
     g64q, gq = to_dev(workload_inputs(w, out_dtype=np.float32)[0], storage)
     out = tnlm.jacobi_step(gq, gq, gq, w.mu, d=w.d, M=w.M, h=w.h)
     torch.cuda.synchronize()
-    idx = sample_idx(w.shape, 200, 5)
+    idx = with_peaks(sample_idx(w.shape, 200, 5), out)
     ref = oracle.jacobi(g64q, g64q, g64q, w.mu, w.d, w.M, w.h, idx=idx)
     eps = 2.0 ** -8 if storage == "bf16" else 2.0 ** -11
     assert_close(host(out).ravel()[idx], ref, FP32_TOL + eps, "f_out")
@@ -123,11 +124,11 @@ def test_energy128_energy_and_adjoint_sampled():
     sth = st.double().cpu().numpy()
     E_sum = 0.25 * float(np.sum(sth[:, :, 1, :]))
     assert abs(E - E_sum) <= 1e-9 * abs(E_sum) + 1e-6, (E, E_sum)
-    idx = sample_idx(w.shape, 64, 6)
+    idx = with_peaks(sample_idx(w.shape, 64, 6), gt)
     N = w.nx * w.ny * w.nz
     ref_st = oracle.stats(f64, f64, w.d, w.M, w.h, idx=idx)
     assert_close(sth[idx // N, :, :, idx % N], ref_st, FP32_TOL, "stats")
-    gidx = idx[::2]
+    gidx = with_peaks(idx[::2], gt)
     rf, ru = oracle.grad_exact_at(f64, f64, w.d, w.M, w.h, gidx)
     assert_close(host(gt).ravel()[gidx], rf + ru, FP32_TOL, "dE/df total")
     # central differences of the FP64 local energy (eps = 1e-3, with a
