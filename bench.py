@@ -99,7 +99,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dtypes", action="store_true",
-                    help="skip the BF16/FP16 storage comparison")
+                    help="skip the BF16/FP16 storage and autograd comparisons")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the TNLM path here is a "
@@ -213,6 +213,34 @@ def main():
                          "jacobi_voxel_updates_per_s":
                              nvox / (ms["jacobi"] / 1e3)}
 
+    # the differentiable form against the plain calls it wraps: energy with
+    # statistics + exact adjoint, vs autograd forward + backward of E(f; f)
+    def time_ms(fn, reps=2):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = EV(), EV()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    def plain():
+        _, st = tnlm.energy(f_a, d=d, M=M, h=h, want_stats=True)
+        return tnlm.grad(f_a, d=d, M=M, h=h, mode="exact", stats=st, total=True)
+
+    def differentiable():
+        fr = f_a.detach().requires_grad_(True)
+        tnlm.tnlm_energy(fr, d, M, h).backward()
+        return fr.grad
+
+    autograd = None
+    if not args.no_dtypes:
+        log("timing the autograd form against the plain calls ...")
+        autograd = {"plain_energy_plus_adjoint_ms": time_ms(plain),
+                    "autograd_forward_backward_ms": time_ms(differentiable)}
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on a sample ...")
@@ -232,6 +260,7 @@ def main():
         "energy": E,
         "jacobi_voxel_updates_per_s": nvox / (ms["jacobi"] / 1e3),
         "storage_dtypes": dtypes,
+        "autograd": autograd,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "paper_context": {"tnlm_e_per_iteration_s": 55.07,
