@@ -64,7 +64,8 @@ def workspace_bytes(shape, d, M, h, op) -> int:
     g = _lib.Geom(*[int(s) for s in shape], int(d), int(M), float(h))
     n = _lib.lib.tnlm_workspace_bytes(ctypes.byref(g), int(op))
     if n == ctypes.c_size_t(-1).value:
-        raise ValueError("invalid geometry or op")
+        # the library's answer for a geometry it rejects (or an unknown op)
+        raise _lib.TNLMError(_lib.EINVAL, "tnlm_workspace_bytes")
     return n
 
 

@@ -151,3 +151,13 @@ def test_package_has_no_cpu_path():
     x = torch.zeros((2, 4, 4, 4))
     with pytest.raises(ValueError, match="GPU"):
         tnlm.jacobi_step(x, x, x, 1.0, d=1, M=1, h=0.1)
+
+
+def test_binding_raises_library_error_for_rejected_geometry():
+    """The binding reports a geometry the library rejects (empty grid, one
+    phase) as the library's status, before any device call."""
+    from paper_1201_2450_amd import ops
+    for shape in ((2, 0, 4, 4), (1, 4, 4, 4)):
+        with pytest.raises(_lib.TNLMError) as ei:
+            ops.workspace_bytes(shape, 1, 1, 0.1, _lib.OP_ENERGY)
+        assert ei.value.code == _lib.EINVAL

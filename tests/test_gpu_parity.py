@@ -32,6 +32,8 @@ CASES = [
     ((2, 4, 4, 1), 1, 2, 0.2, "uniform"),      # nz = 1
     ((3, 12, 10, 20), 1, 2, 0.03, "uniform"),  # deep-underflow / overflow path
     ((2, 6, 7, 8), 1, 0, 0.05, "phantom"),     # M = 0: single candidate
+    ((3, 6, 1, 12), 1, 2, 0.05, "phantom"),    # ny = 1
+    ((2, 7, 8, 9), 1, 5, 0.05, "phantom"),     # M = 5: beyond the tiled kernels
 ]
 
 
@@ -157,6 +159,19 @@ def test_adjoint_image_equal_to_weight_source_instance(M, storage):
     rf, ru = oracle.grad_exact_at(f64, f64, d, M, h, idx)
     assert_close(host(gs_f).ravel()[idx], rf, FP32_TOL, "dE/df vs oracle")
     assert_close(host(gs_u).ravel()[idx], ru, FP32_TOL, "dE/du vs oracle")
+
+
+def test_empty_and_too_few_phases_are_rejected_before_any_launch():
+    """Empty volumes and a single phase are invalid geometries: the library
+    returns EINVAL (no kernel runs) and the binding raises."""
+    for shape in ((2, 0, 4, 4), (2, 4, 0, 4), (2, 4, 4, 0), (1, 4, 4, 4)):
+        say(f"rejected {shape}")
+        x = torch.zeros(shape, device=device())
+        with pytest.raises(tnlm.TNLMError):
+            tnlm.jacobi_step(x, x, x, 0.5, d=1, M=1, h=0.1)
+        with pytest.raises(tnlm.TNLMError):
+            tnlm.energy(x, d=1, M=1, h=0.1)
+    torch.cuda.synchronize()
 
 
 def test_constant_volume_is_a_fixed_point_on_gpu():
