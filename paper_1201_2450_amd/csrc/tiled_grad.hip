@@ -16,13 +16,14 @@
 // position onto the grid voxel it clamps to, which is the chain rule through
 // the clamp-to-edge extension.
 //
-// Work layout (one workgroup = 8 waves): a workgroup owns 2 (x) x 56 (y) x 16
-// (z) padded outputs of one phase; lanes run along y in 32-lane segments
-// (two halo rows on each side: one for the distance box, one for the Gv box,
-// so 28 outputs per segment); each lane keeps 2 (x) x 4 (z) outputs. Waves
-// w and w+4 own the same outputs and split the (dy, dz) offset pairs between
-// them (alternate pairs), sharing one LDS tile; their partial sums are added
-// in a fixed order at the end, so two waves per SIMD run on 124 KB of LDS. Per
+// Work layout: a workgroup owns 2 (x) x 56 (y) x 4*ZB (z) padded outputs of
+// one phase (ZB z-blocks: 2 when u = f, else 4); lanes run along y in 32-lane
+// segments (two halo rows on each side: one for the distance box, one for the
+// Gv box, so 28 outputs per segment); each lane keeps 2 (x) x 4 (z) outputs.
+// Two waves own each z-block and split the (dy, dz) offset pairs between them
+// (alternate pairs), sharing one LDS tile; their partial sums are added in a
+// fixed order at the end. With ZB = 2 two workgroups (8 waves) share a CU, so
+// one stages its tile while the other computes. Per
 // search offset a lane builds D on its block grown by one voxel in x and z
 // (box sums of squared differences as in the forward kernel), forms Gv there,
 // and box-sums Gv back onto its outputs; the 3-tap box sums along z and x
@@ -47,20 +48,29 @@ constexpr int kEZ = kBZ + 2;      // Gv positions per lane in z
 constexpr int kSX = kBX + 4;      // squared-difference planes per lane
 constexpr int kSZ = kBZ + 4;      // squared-difference z per lane
 constexpr int kSegOut = 28;       // outputs per 32-lane segment
-constexpr int kWaves = 4;             // z-blocks per workgroup
 #ifndef TNLM_GRAD_SETS
 #define TNLM_GRAD_SETS 2
 #endif
 constexpr int kSets = TNLM_GRAD_SETS;  // waves per z-block, splitting the offset pairs
-constexpr int kThreads = kSets * 64 * kWaves;
 constexpr int kTY = 2 * kSegOut;  // 56
-constexpr int kTZ = kWaves * kBZ; // 16
 constexpr float kLog2e = 1.4426950408889634f;
 
-template <int M>
+// Workgroup shape per instance: the u = f instance (no f_j tile) takes two
+// z-blocks, so its LDS tile (~67 KB at M = 3) lets two workgroups share a CU
+// and one stages while the other computes; the general instance, with f_j
+// staged too, takes four z-blocks (one workgroup of eight waves per CU).
+template <bool SAME>
+struct Lay {
+    static constexpr int ZB = SAME ? 2 : 4;            // z-blocks per workgroup
+    static constexpr int THREADS = kSets * 64 * ZB;
+    static constexpr int TZ = ZB * kBZ;               // padded z outputs per workgroup
+};
+constexpr int kMinTZ = Lay<true>::TZ;
+
+template <int M, bool SAME>
 struct GG {
-    static constexpr int YL = kTY + 4 + 2 * M;  // rows Y0-2-M .. Y0+kTY+1+M
-    static constexpr int ZL = kTZ + 4 + 2 * M;  // z    Z0-2-M .. Z0+kTZ+1+M
+    static constexpr int YL = kTY + 4 + 2 * M;           // rows Y0-2-M .. Y0+kTY+1+M
+    static constexpr int ZL = Lay<SAME>::TZ + 4 + 2 * M;  // z    Z0-2-M .. Z0+TZ+1+M
     static constexpr int RU = (kSX * ZL) | 1;      // u_j row: kSX planes
     static constexpr int RV = (kEX * ZL) | 1;      // f_j row: kEX planes
     static constexpr int RS = (2 * kEX * ZL) | 1;  // (L2, e2) row: pairs, kEX planes
@@ -89,10 +99,13 @@ __device__ __forceinline__ int clampi(int a, int lo, int hi)
 // SAME: the image is the weight source (f and u are one volume), so f_j is
 // the staged u_j and the residual r is the centre squared-difference term.
 template <typename T, int M, bool SAME>
-__global__ void __launch_bounds__(kThreads) grad_tiled_kernel(Geo g, GradArgs a, float *gpad,
-                                                              GradGrid gg)
+__global__ void __launch_bounds__(Lay<SAME>::THREADS)
+    grad_tiled_kernel(Geo g, GradArgs a, float *gpad, GradGrid gg)
 {
-    using G = GG<M>;
+    using G = GG<M, SAME>;
+    constexpr int kWaves = Lay<SAME>::ZB;
+    constexpr int kThreads = Lay<SAME>::THREADS;
+    constexpr int kTZ = Lay<SAME>::TZ;
     __shared__ float sU[G::YL * G::RU];
     __shared__ float sF[SAME ? 1 : G::YL * G::RV];  // f_j (u_j when SAME)
     __shared__ float sS[G::YL * G::RS];  // (-lse*log2e, e2) side by side
@@ -388,7 +401,7 @@ __global__ void __launch_bounds__(kThreads) grad_tiled_kernel(Geo g, GradArgs a,
     __syncthreads();
     float *xfer = sU;  // the staging tile is free now
     constexpr int kPer = 2 * kBX * kBZ;
-    static_assert((kSets - 1) * kWaves * 64 * kPer <= GG<M>::YL * GG<M>::RU, "transfer fits");
+    static_assert((kSets - 1) * kWaves * 64 * kPer <= G::YL * G::RU, "transfer fits");
     if (half > 0) {
         float *xs = xfer + (((half - 1) * kWaves + wave) * 64 + lane) * kPer;
 #pragma unroll
@@ -456,9 +469,21 @@ __global__ void __launch_bounds__(256) fold_kernel(Geo g, const float *gpad, flo
     }
 }
 
-template <typename T, bool SAME>
-void launch_m(const Geo &g, const GradArgs &a, float *gpad, const GradGrid &gg, hipStream_t s)
+GradGrid grad_grid(const Geo &g, int tz)
 {
+    GradGrid gg;
+    gg.ntx = (g.nx + 2 + kBX - 1) / kBX;
+    gg.nty = (g.ny + 2 + kTY - 1) / kTY;
+    gg.ntz = (g.nz + 2 + tz - 1) / tz;
+    gg.nblocks = g.np * gg.ntx * gg.nty * gg.ntz;
+    return gg;
+}
+
+template <typename T, bool SAME>
+void launch_m(const Geo &g, const GradArgs &a, float *gpad, hipStream_t s)
+{
+    constexpr int kThreads = Lay<SAME>::THREADS;
+    const GradGrid gg = grad_grid(g, Lay<SAME>::TZ);
     switch (g.M) {
     case 1:
         grad_tiled_kernel<T, 1, SAME><<<gg.nblocks, kThreads, 0, s>>>(g, a, gpad, gg);
@@ -476,23 +501,13 @@ void launch_m(const Geo &g, const GradArgs &a, float *gpad, const GradGrid &gg, 
 }
 
 template <typename T>
-hipError_t launch_t(const Geo &g, const GradArgs &a, float *gpad, const GradGrid &gg, hipStream_t s)
+hipError_t launch_t(const Geo &g, const GradArgs &a, float *gpad, hipStream_t s)
 {
     if (a.u == a.f)
-        launch_m<T, true>(g, a, gpad, gg, s);
+        launch_m<T, true>(g, a, gpad, s);
     else
-        launch_m<T, false>(g, a, gpad, gg, s);
+        launch_m<T, false>(g, a, gpad, s);
     return hipGetLastError();
-}
-
-GradGrid grad_grid(const Geo &g)
-{
-    GradGrid gg;
-    gg.ntx = (g.nx + 2 + kBX - 1) / kBX;
-    gg.nty = (g.ny + 2 + kTY - 1) / kTY;
-    gg.ntz = (g.nz + 2 + kTZ - 1) / kTZ;
-    gg.nblocks = g.np * gg.ntx * gg.nty * gg.ntz;
-    return gg;
 }
 
 }  // namespace
@@ -505,7 +520,7 @@ bool grad_tiled_supported(const Geo &g)
     if ((int64_t)g.ny * g.nz * (int64_t)sizeof(float) >= (int64_t(1) << 32))
         return false;
     const int64_t nb = (int64_t)g.np * ((g.nx + 2 + kBX - 1) / kBX) *
-                       ((g.ny + 2 + kTY - 1) / kTY) * ((g.nz + 2 + kTZ - 1) / kTZ);
+                       ((g.ny + 2 + kTY - 1) / kTY) * ((g.nz + 2 + kMinTZ - 1) / kMinTZ);
     return nb < (int64_t(1) << 31);
 }
 
@@ -516,19 +531,18 @@ size_t grad_tiled_pad_bytes(const Geo &g)
 
 hipError_t launch_grad_tiled(const Geo &g, int dtype, const GradArgs &a, float *gpad, hipStream_t s)
 {
-    const GradGrid gg = grad_grid(g);
     hipError_t e;
     // weight part needed for grad_u; the kernel always writes it to gpad
     float *gp = a.grad_u ? gpad : nullptr;
     switch (dtype) {
     case TNLM_F32:
-        e = launch_t<float>(g, a, gp, gg, s);
+        e = launch_t<float>(g, a, gp, s);
         break;
     case TNLM_BF16:
-        e = launch_t<bf16_t>(g, a, gp, gg, s);
+        e = launch_t<bf16_t>(g, a, gp, s);
         break;
     default:
-        e = launch_t<_Float16>(g, a, gp, gg, s);
+        e = launch_t<_Float16>(g, a, gp, s);
         break;
     }
     if (e != hipSuccess || !a.grad_u)
