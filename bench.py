@@ -191,6 +191,17 @@ def main():
                 "kernel": "tnlm_jacobi_step",
                 "algorithmic_flop_per_launch": alg_flop}
 
+    def time_ms(fn, reps=2):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = EV(), EV()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
     dtypes = {}
     if not args.no_dtypes:
         for name, dt in (("bf16", torch.bfloat16), ("f16", torch.float16)):
@@ -206,40 +217,46 @@ def main():
             e1.record()
             torch.cuda.synchronize()
             jms = e0.elapsed_time(e1) / reps
+
+            def energy_adjoint():
+                _, st = tnlm.energy(gq, d=d, M=M, h=h, want_stats=True)
+                return tnlm.grad(gq, d=d, M=M, h=h, mode="exact", stats=st, total=True)
+
+            eams = time_ms(energy_adjoint)
             dtypes[name] = {"jacobi_ms": jms,
-                            "jacobi_voxel_updates_per_s": nvox / (jms / 1e3)}
+                            "jacobi_voxel_updates_per_s": nvox / (jms / 1e3),
+                            "energy_plus_adjoint_ms": eams}
             del gq, outq
         dtypes["f32"] = {"jacobi_ms": ms["jacobi"],
                          "jacobi_voxel_updates_per_s":
-                             nvox / (ms["jacobi"] / 1e3)}
+                             nvox / (ms["jacobi"] / 1e3),
+                         "energy_plus_adjoint_ms":
+                             ms["energy_fwd"] + ms["adjoint"]}
 
     # the differentiable form against the plain calls it wraps: energy with
     # statistics + exact adjoint, vs autograd forward + backward of E(f; f)
-    def time_ms(fn, reps=2):
-        fn()
-        torch.cuda.synchronize()
-        e0, e1 = EV(), EV()
-        e0.record()
-        for _ in range(reps):
-            fn()
-        e1.record()
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / reps
+    def autograd_vs_plain(x, dd, MM, hh):
+        def plain():
+            _, st = tnlm.energy(x, d=dd, M=MM, h=hh, want_stats=True)
+            return tnlm.grad(x, d=dd, M=MM, h=hh, mode="exact", stats=st, total=True)
 
-    def plain():
-        _, st = tnlm.energy(f_a, d=d, M=M, h=h, want_stats=True)
-        return tnlm.grad(f_a, d=d, M=M, h=h, mode="exact", stats=st, total=True)
+        def differentiable():
+            fr = x.detach().requires_grad_(True)
+            tnlm.tnlm_energy(fr, dd, MM, hh).backward()
+            return fr.grad
 
-    def differentiable():
-        fr = f_a.detach().requires_grad_(True)
-        tnlm.tnlm_energy(fr, d, M, h).backward()
-        return fr.grad
+        return {"plain_energy_plus_adjoint_ms": time_ms(plain),
+                "autograd_forward_backward_ms": time_ms(differentiable)}
 
     autograd = None
     if not args.no_dtypes:
         log("timing the autograd form against the plain calls ...")
-        autograd = {"plain_energy_plus_adjoint_ms": time_ms(plain),
-                    "autograd_forward_backward_ms": time_ms(differentiable)}
+        autograd = {w.name: autograd_vs_plain(f_a, d, M, h)}
+        we = WORKLOADS["energy128"]
+        fe = torch.from_numpy(workload_inputs(we, out_dtype=np.float32)[0]).to(dev)
+        autograd[we.name] = dict(autograd_vs_plain(fe, we.d, we.M, we.h),
+                                 shape=list(we.shape), window=2 * we.M + 1)
+        del fe
 
     cpu = None
     if not args.no_cpu_baseline:
