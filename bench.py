@@ -40,9 +40,10 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def measured_traffic():
-    """HBM bytes per Jacobi launch from the committed rocprofv3 counter
-    summary, or None when the kernel source changed since it was taken."""
+def profile_figures():
+    """HBM bytes and counter FP32 flop per Jacobi launch from the committed
+    rocprofv3 counter summary, or {} when the kernel source changed since
+    the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "jacobi_enh256_traffic.txt")
     src = os.path.join(ROOT, "paper_1201_2450_amd", "csrc", "tiled_fwd.hip")
@@ -54,10 +55,13 @@ def measured_traffic():
                 kv[k.strip()] = v.strip()
         sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
         if kv.get("source_sha256_tiled_fwd_hip") != sha:
-            return None
-        return float(kv["traffic_bytes"])
+            return {}
+        out = {"traffic": float(kv["traffic_bytes"])}
+        if "counter_flop_per_launch" in kv:
+            out["counter_flop"] = float(kv["counter_flop_per_launch"])
+        return out
     except (OSError, KeyError, ValueError):
-        return None
+        return {}
 
 
 def cpu_baseline(w, target_s):
@@ -184,12 +188,20 @@ def main():
     # dominant kernel: the Gauss-Jacobi step
     alg_flop = FLOP_PER_UPDATE_PER_OFFSET * W * nvox
     achieved = alg_flop / (ms["jacobi"] / 1e3) / 1e12
+    prof = profile_figures()
     roofline = {"bound": "alu", "achieved": achieved,
                 "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP32_TFLOPS,
-                "traffic": measured_traffic(),
+                "traffic": prof.get("traffic"),
                 "kernel": "tnlm_jacobi_step",
                 "algorithmic_flop_per_launch": alg_flop}
+    if "counter_flop" in prof:
+        # the hardware's count of FP32 operations (64 x (ADD + MUL + TRANS +
+        # 2 FMA) wave instructions) over the same measured launch time
+        c = prof["counter_flop"] / (ms["jacobi"] / 1e3) / 1e12
+        roofline["counter_achieved"] = c
+        roofline["counter_frac"] = c / PEAK_FP32_TFLOPS
+        roofline["counter_flop_per_launch"] = prof["counter_flop"]
 
     def time_ms(fn, reps=2):
         fn()
