@@ -1,5 +1,5 @@
 // Tiled forward TNLM kernels for 3x3x3 patches (d = 1) and search radius
-// M = 1..4: the Gauss-Jacobi step (Eq. (8)), the Eq. (6) operator, the
+// M = 1..5: the Gauss-Jacobi step (Eq. (8)), the Eq. (6) operator, the
 // per-voxel log-normalisers of the weights (Eq. (3)) and the energy with its
 // per-voxel statistics.
 //
@@ -44,6 +44,7 @@ namespace {
 constexpr int kBZ = 4;              // output z per lane
 constexpr int kSegOut = 30;         // output rows per 32-lane segment
 constexpr int kTY = kSegOut;        // tile extent in y (one segment)
+constexpr int kMaxTiledM = 5;       // search radii with a tiled instance
 constexpr float kZOverflow = 1.2676506e30f;  // 2^100
 
 // Tile shape: BX output x-planes per lane, ZB z-blocks per tile, HALVES sets
@@ -514,8 +515,10 @@ hipError_t launch_t(const Geo &g, int mode, const FwdArgs &a, const TileGrid &tg
         return launch_m<T, 2>(g, mode, a, tg, s);
     case 3:
         return launch_m<T, 3>(g, mode, a, tg, s);
-    default:
+    case 4:
         return launch_m<T, 4>(g, mode, a, tg, s);
+    default:
+        return launch_m<T, 5>(g, mode, a, tg, s);
     }
 }
 
@@ -534,7 +537,7 @@ TileGrid tile_grid(const Geo &g)
 bool fwd_tiled_supported(const Geo &g, int mode)
 {
     (void)mode;  // log-normaliser requests only; w goes to the generic path
-    if (g.d != 1 || g.M < 1 || g.M > 4)
+    if (g.d != 1 || g.M < 1 || g.M > kMaxTiledM)
         return false;
     // staging addresses a cell within an x-plane by a 32-bit byte offset
     if ((int64_t)g.ny * g.nz * (int64_t)sizeof(float) >= (int64_t(1) << 32))

@@ -1,5 +1,5 @@
 // Tiled exact gradient of the TNLM energy for 3x3x3 patches (d = 1) and
-// search radius M = 1..4, gather form, from the saved per-voxel statistics
+// search radius M = 1..5, gather form, from the saved per-voxel statistics
 // (log-normaliser and e of every voxel and direction).
 //
 // For output phase k, neighbour j = k+s and search offset delta:
@@ -56,21 +56,23 @@ constexpr int kTY = 2 * kSegOut;  // 56
 constexpr float kLog2e = 1.4426950408889634f;
 
 // Workgroup shape per instance: the u = f instance (no f_j tile) takes two
-// z-blocks, so its LDS tile (~67 KB at M = 3) lets two workgroups share a CU
-// and one stages while the other computes; the general instance, with f_j
-// staged too, takes four z-blocks (one workgroup of eight waves per CU).
-template <bool SAME>
+// z-blocks up to M = 4, so its LDS tile (~67 KB at M = 3, 77 KB at M = 4)
+// lets two workgroups share a CU and one stages while the other computes;
+// the general instance, with f_j staged too, and M = 5 take four z-blocks
+// (one workgroup of eight waves per CU).
+constexpr int kMaxTiledM = 5;  // search radii with a tiled instance
+template <bool SAME, int M>
 struct Lay {
-    static constexpr int ZB = SAME ? 2 : 4;            // z-blocks per workgroup
+    static constexpr int ZB = (SAME && M <= 4) ? 2 : 4;  // z-blocks per workgroup
     static constexpr int THREADS = kSets * 64 * ZB;
-    static constexpr int TZ = ZB * kBZ;               // padded z outputs per workgroup
+    static constexpr int TZ = ZB * kBZ;                 // padded z outputs per workgroup
 };
-constexpr int kMinTZ = Lay<true>::TZ;
+constexpr int kMinTZ = Lay<true, 1>::TZ;
 
 template <int M, bool SAME>
 struct GG {
-    static constexpr int YL = kTY + 4 + 2 * M;           // rows Y0-2-M .. Y0+kTY+1+M
-    static constexpr int ZL = Lay<SAME>::TZ + 4 + 2 * M;  // z    Z0-2-M .. Z0+TZ+1+M
+    static constexpr int YL = kTY + 4 + 2 * M;              // rows Y0-2-M .. Y0+kTY+1+M
+    static constexpr int ZL = Lay<SAME, M>::TZ + 4 + 2 * M;  // z    Z0-2-M .. Z0+TZ+1+M
     static constexpr int RU = (kSX * ZL) | 1;      // u_j row: kSX planes
     static constexpr int RV = (kEX * ZL) | 1;      // f_j row: kEX planes
     static constexpr int RS = (2 * kEX * ZL) | 1;  // (L2, e2) row: pairs, kEX planes
@@ -99,13 +101,13 @@ __device__ __forceinline__ int clampi(int a, int lo, int hi)
 // SAME: the image is the weight source (f and u are one volume), so f_j is
 // the staged u_j and the residual r is the centre squared-difference term.
 template <typename T, int M, bool SAME>
-__global__ void __launch_bounds__(Lay<SAME>::THREADS)
+__global__ void __launch_bounds__((Lay<SAME, M>::THREADS))
     grad_tiled_kernel(Geo g, GradArgs a, float *gpad, GradGrid gg)
 {
     using G = GG<M, SAME>;
-    constexpr int kWaves = Lay<SAME>::ZB;
-    constexpr int kThreads = Lay<SAME>::THREADS;
-    constexpr int kTZ = Lay<SAME>::TZ;
+    constexpr int kWaves = Lay<SAME, M>::ZB;
+    constexpr int kThreads = Lay<SAME, M>::THREADS;
+    constexpr int kTZ = Lay<SAME, M>::TZ;
     __shared__ float sU[G::YL * G::RU];
     __shared__ float sF[SAME ? 1 : G::YL * G::RV];  // f_j (u_j when SAME)
     __shared__ float sS[G::YL * G::RS];  // (-lse*log2e, e2) side by side
@@ -479,23 +481,32 @@ GradGrid grad_grid(const Geo &g, int tz)
     return gg;
 }
 
+template <typename T, int M, bool SAME>
+void launch_one(const Geo &g, const GradArgs &a, float *gpad, hipStream_t s)
+{
+    using L = Lay<SAME, M>;
+    const GradGrid gg = grad_grid(g, L::TZ);
+    grad_tiled_kernel<T, M, SAME><<<gg.nblocks, L::THREADS, 0, s>>>(g, a, gpad, gg);
+}
+
 template <typename T, bool SAME>
 void launch_m(const Geo &g, const GradArgs &a, float *gpad, hipStream_t s)
 {
-    constexpr int kThreads = Lay<SAME>::THREADS;
-    const GradGrid gg = grad_grid(g, Lay<SAME>::TZ);
     switch (g.M) {
     case 1:
-        grad_tiled_kernel<T, 1, SAME><<<gg.nblocks, kThreads, 0, s>>>(g, a, gpad, gg);
+        launch_one<T, 1, SAME>(g, a, gpad, s);
         break;
     case 2:
-        grad_tiled_kernel<T, 2, SAME><<<gg.nblocks, kThreads, 0, s>>>(g, a, gpad, gg);
+        launch_one<T, 2, SAME>(g, a, gpad, s);
         break;
     case 3:
-        grad_tiled_kernel<T, 3, SAME><<<gg.nblocks, kThreads, 0, s>>>(g, a, gpad, gg);
+        launch_one<T, 3, SAME>(g, a, gpad, s);
+        break;
+    case 4:
+        launch_one<T, 4, SAME>(g, a, gpad, s);
         break;
     default:
-        grad_tiled_kernel<T, 4, SAME><<<gg.nblocks, kThreads, 0, s>>>(g, a, gpad, gg);
+        launch_one<T, 5, SAME>(g, a, gpad, s);
         break;
     }
 }
@@ -514,7 +525,7 @@ hipError_t launch_t(const Geo &g, const GradArgs &a, float *gpad, hipStream_t s)
 
 bool grad_tiled_supported(const Geo &g)
 {
-    if (g.d != 1 || g.M < 1 || g.M > 4)
+    if (g.d != 1 || g.M < 1 || g.M > kMaxTiledM)
         return false;
     // staging addresses a cell within an x-plane by a 32-bit byte offset
     if ((int64_t)g.ny * g.nz * (int64_t)sizeof(float) >= (int64_t(1) << 32))

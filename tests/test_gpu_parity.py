@@ -33,7 +33,8 @@ CASES = [
     ((3, 12, 10, 20), 1, 2, 0.03, "uniform"),  # deep-underflow / overflow path
     ((2, 6, 7, 8), 1, 0, 0.05, "phantom"),     # M = 0: single candidate
     ((3, 6, 1, 12), 1, 2, 0.05, "phantom"),    # ny = 1
-    ((2, 7, 8, 9), 1, 5, 0.05, "phantom"),     # M = 5: beyond the tiled kernels
+    ((2, 7, 8, 9), 1, 5, 0.05, "phantom"),     # M = 5: largest tiled window
+    ((2, 6, 7, 8), 1, 6, 0.05, "phantom"),     # M = 6: generic kernels
 ]
 
 
@@ -138,7 +139,7 @@ def test_results_are_bitwise_deterministic():
         assert np.array_equal(a.view(np.uint8), b.view(np.uint8))
 
 
-@pytest.mark.parametrize("M", [1, 2, 3, 4])
+@pytest.mark.parametrize("M", [1, 2, 3, 4, 5])
 @pytest.mark.parametrize("storage", ["f32", "bf16"])
 def test_adjoint_image_equal_to_weight_source_instance(M, storage):
     """The adjoint has an instance for u and f being one buffer (f_j read

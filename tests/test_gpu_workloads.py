@@ -59,6 +59,29 @@ def test_interior_tiles_forward_modes():
     assert abs(E - E_ref) <= FP32_TOL * abs(E_ref), (E, E_ref)
 
 
+def test_interior_tiles_largest_tiled_window_sampled():
+    """M = 5 (11^3 window), the largest radius with tiled kernels, on a grid
+    with interior tiles: Jacobi step, Eq. 6 operator and log-normalisers at
+    sampled voxels (plus each field's peak)."""
+    shape, d, M, h, mu = (2, 20, 70, 40), 1, 5, 0.05, 0.6
+    say(f"interior forward M=5 {shape}")
+    u64, u = to_dev(inputs(shape, "phantom", 26))
+    f64, f = to_dev(inputs(shape, "phantom", 27))
+    g64, g = to_dev(inputs(shape, "phantom", 28))
+    out = tnlm.jacobi_step(u, f, g, mu, d=d, M=M, h=h)
+    g6 = tnlm.grad(f, u=u, d=d, M=M, h=h, mode="eq6")
+    _, lse = tnlm.weights(u, d=d, M=M, h=h)
+    torch.cuda.synchronize()
+    idx = with_peaks(sample_idx(shape, 300, 7), out, g6)
+    assert_close(host(out).ravel()[idx],
+                 oracle.jacobi(u64, f64, g64, mu, d, M, h, idx=idx), FP32_TOL, "jacobi")
+    assert_close(host(g6).ravel()[idx],
+                 oracle.grad_eq6(u64, f64, d, M, h, idx=idx), FP32_TOL, "eq6")
+    N = int(np.prod(shape[1:]))
+    st = oracle.stats(u64, u64, d, M, h, idx=idx)
+    assert_close(host(lse)[idx // N, :, idx % N], st[:, :, 0], FP32_TOL, "lse")
+
+
 def test_interior_tiles_exact_gradient_sampled():
     shape, d, M, h = (2, 12, 116, 36), 1, 2, 0.05
     say(f"interior gradient {shape}")
