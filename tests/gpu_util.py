@@ -76,6 +76,28 @@ def assert_close(got, ref, tol, what):
     assert e <= tol, f"{what}: normwise rel err {e:.3e} > {tol:.1e}"
 
 
+def assert_close_faces(got, ref, idx, shape, what):
+    """The weight part of the exact gradient, dE/du, at flat indices idx:
+    FP32_TOL inside the grid and 2 FP32_TOL on its faces, where the
+    derivatives of the clamped copies of a face voxel are added (chain rule
+    through clamp-to-edge: large terms of both signs). Both relative to the
+    largest reference value among the samples."""
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    pos = np.unravel_index(np.asarray(idx), shape)
+    face = np.zeros(len(idx), dtype=bool)
+    for ax in (1, 2, 3):
+        face |= (pos[ax] == 0) | (pos[ax] == shape[ax] - 1)
+    scale = np.abs(ref).max()
+    err = np.abs(got - ref)
+    e_in = err[~face].max() / scale if (~face).any() else 0.0
+    e_face = err[face].max() / scale if face.any() else 0.0
+    say(f"  {what}: inside {e_in:.3e} (tol {FP32_TOL:.1e}), faces {e_face:.3e} "
+        f"(tol {2 * FP32_TOL:.1e})")
+    assert np.isfinite(got).all(), f"{what}: non-finite output"
+    assert e_in <= FP32_TOL and e_face <= 2 * FP32_TOL, (what, e_in, e_face)
+
+
 def inputs(shape, kind, seed):
     """Seeded float64 volumes of a given flavour."""
     if kind == "phantom":
