@@ -31,7 +31,8 @@
 //   * weights are accumulated as exp2(c2 (ref - D)) with ref the distance of
 //     the zero offset, so the zero-offset term is exactly 1 and the sum never
 //     underflows; if some far better match overflows the sum (>= 2^100) the
-//     workgroup redoes that direction with ref = min D over the window.
+//     workgroup redoes that direction with the reference lowered by 100 in the
+//     exponent, and if that still overflows, with ref = min D over the window.
 #include <math.h>
 
 #include <type_traits>
@@ -378,41 +379,59 @@ __global__ void __launch_bounds__(C::THREADS) fwd_tiled_kernel(Geo g, FwdArgs a,
             }
         }
 
-        // overflow of the shifted sum: redo this direction relative to min D,
-        // by the first half alone over every offset
-        if (half == 0) {
-            bool bad = false;
+        // overflow of the shifted sum (decided for the whole workgroup)
+        auto overflowed = [&]() {
+            if (half == 0) {
+                bool bad = false;
 #pragma unroll
-            for (int xo = 0; xo < BX; ++xo)
+                for (int xo = 0; xo < BX; ++xo)
 #pragma unroll
-                for (int k = 0; k < kBZ; ++k)
-                    bad |= out_ok(xo, k) && !(A.Z[xo][k] < kZOverflow);
-            if (__any(bad))
-                s_redo = 1;
-        }
-        __syncthreads();
-        const int redo = s_redo;
-        __syncthreads();
-        if (tid == 0)
-            s_redo = 0;
-        if (redo) {
+                    for (int k = 0; k < kBZ; ++k)
+                        bad |= out_ok(xo, k) && !(A.Z[xo][k] < kZOverflow);
+                if (__any(bad))
+                    s_redo = 1;
+            }
+            __syncthreads();
+            const int r = s_redo;
+            __syncthreads();
+            if (tid == 0)
+                s_redo = 0;
+            return r;
+        };
+        if (overflowed()) {
             const int p0 = half == 0 ? 0 : S * S;  // the second half only stages
+            // First retry, by the first half alone over every offset: the
+            // same reference lowered by 100 in the exponent. Every term
+            // shrinks by 2^-100, so a sum that reached 2^100 fits again unless
+            // some candidate beats the zero offset by more than 2^228; the
+            // zero-offset term stays a normal float (2^-100), so nothing that
+            // matters underflows.
 #pragma unroll
             for (int xo = 0; xo < BX; ++xo)
 #pragma unroll
                 for (int k = 0; k < kBZ; ++k)
-                    A.N[xo][k] = INFINITY;
-            sweep(j, min_c{}, std::true_type{}, p0, 1);
-#pragma unroll
-            for (int xo = 0; xo < BX; ++xo)
-#pragma unroll
-                for (int k = 0; k < kBZ; ++k) {
-                    const float m = A.N[xo][k];
-                    // keep NaN inputs NaN; otherwise the exact minimum
-                    A.cref[xo][k] = (m == m) ? m * g.c2 : A.cref[xo][k];
-                }
+                    A.cref[xo][k] -= 100.f;
             zero_acc();
             sweep(j, acc_c{}, std::true_type{}, p0, 1);
+            if (overflowed()) {
+                // still out of range: redo relative to the exact minimum
+#pragma unroll
+                for (int xo = 0; xo < BX; ++xo)
+#pragma unroll
+                    for (int k = 0; k < kBZ; ++k)
+                        A.N[xo][k] = INFINITY;
+                sweep(j, min_c{}, std::true_type{}, p0, 1);
+#pragma unroll
+                for (int xo = 0; xo < BX; ++xo)
+#pragma unroll
+                    for (int k = 0; k < kBZ; ++k) {
+                        const float m = A.N[xo][k];
+                        // keep NaN inputs NaN; otherwise the exact minimum
+                        A.cref[xo][k] = (m == m) ? m * g.c2 : A.cref[xo][k];
+                    }
+                zero_acc();
+                sweep(j, acc_c{}, std::true_type{}, p0, 1);
+            }
         }
         if (half != 0)
             continue;
