@@ -34,6 +34,7 @@ METRIC = ("TNLM voxel-updates/s + fwd/adjoint ms, 10×256²×128, "
 # MI355X FP32 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2 (packed)
 # x 2.4 GHz
 PEAK_FP32_TFLOPS = 157.3
+PEAK_FP32_NONPACKED_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 # algorithmic flops per Jacobi voxel-update and search offset, patch 3^3:
 # squared difference 2 + separable 3-tap box sums 6 (once per link), then per
 # direction: exponent 2, numerator FMA 2, normaliser add 1 (x2 directions)
@@ -259,6 +260,10 @@ def main():
                 "traffic": prof.get("traffic"),
                 "kernel": "tnlm_jacobi_step",
                 "algorithmic_flop_per_launch": alg_flop}
+    # without packed FP32 (disabled in this build) the vector peak is half:
+    # 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz
+    roofline["peak_without_packed_fp32"] = PEAK_FP32_NONPACKED_TFLOPS
+    roofline["frac_without_packed_fp32"] = achieved / PEAK_FP32_NONPACKED_TFLOPS
     if "counter_flop" in prof:
         # the hardware's count of FP32 operations (64 x (ADD + MUL + TRANS +
         # 2 FMA) wave instructions) over the same measured launch time
@@ -266,6 +271,7 @@ def main():
         roofline["counter_achieved"] = c
         roofline["counter_frac"] = c / PEAK_FP32_TFLOPS
         roofline["counter_flop_per_launch"] = prof["counter_flop"]
+        roofline["counter_frac_without_packed_fp32"] = c / PEAK_FP32_NONPACKED_TFLOPS
 
     def time_ms(fn, reps=2):
         fn()
