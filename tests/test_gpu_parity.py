@@ -200,6 +200,37 @@ def test_empty_and_too_few_phases_are_rejected_before_any_launch():
     torch.cuda.synchronize()
 
 
+def test_calls_run_on_the_callers_stream_and_share_no_state():
+    """Each call is enqueued on the caller's current stream and keeps no
+    state: the same calls issued on two side streams at once (default
+    priority) give bitwise the results of the default stream."""
+    shape, d, M, h = (3, 16, 31, 40), 1, 3, 0.05
+    say(f"streams {shape}")
+    _, u = to_dev(inputs(shape, "phantom", 50))
+    _, v = to_dev(inputs(shape, "phantom", 51))
+
+    def work(x):
+        j = tnlm.jacobi_step(x, x, x, 0.5, d=d, M=M, h=h)
+        e, st = tnlm.energy(x, d=d, M=M, h=h, want_stats=True)
+        g = tnlm.grad(x, d=d, M=M, h=h, mode="exact", stats=st, total=True)
+        return j, e, g
+
+    ref = [work(u), work(v)]
+    torch.cuda.synchronize()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    s1.wait_stream(torch.cuda.current_stream())
+    s2.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s1):
+        out1 = work(u)
+    with torch.cuda.stream(s2):
+        out2 = work(v)
+    s1.synchronize()
+    s2.synchronize()
+    for got, want in zip(out1 + out2, ref[0] + ref[1]):
+        assert torch.equal(got.view(torch.int32) if got.dtype == torch.float32 else got,
+                           want.view(torch.int32) if want.dtype == torch.float32 else want)
+
+
 def test_constant_volume_is_a_fixed_point_on_gpu():
     shape = (3, 20, 9, 33)
     say(f"constant fixed point {shape}")
