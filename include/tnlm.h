@@ -32,7 +32,12 @@
  *             otherwise, allocated and owned by the caller. The library
  *             allocates nothing, keeps no state between calls and is
  *             thread-safe. `stream` is a hipStream_t (NULL = null stream);
- *             calls are asynchronous and ordered on that stream.
+ *             calls are asynchronous and ordered on that stream. No call
+ *             clears memory, synchronises or allocates, so calls may be
+ *             captured in a HIP graph and replayed.
+ * Speed       patch_r = 1 with 1 <= search_r <= 5 runs LDS-tiled kernels;
+ *             other geometries run a one-thread-per-voxel path that is much
+ *             slower. Both follow the same definitions.
  * Aliasing    u may equal f (weights from the current iterate, as in the
  *             enhancement algorithm). Outputs must not overlap any input
  *             (TNLM_EALIAS); callers ping-pong buffers instead.
