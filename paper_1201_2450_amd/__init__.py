@@ -10,7 +10,8 @@ with a thin PyTorch binding (device memory and streams only):
   TNLMEnergy / tnlm_energy                 autograd wrapper
   enhance(...), descend(...)               host drivers
 
-Importing fails if libtnlm.so has not been built: there is no CPU path.
+The library libtnlm.so is loaded on the first call; that call raises
+ImportError if it has not been built: there is no CPU path.
 """
 from . import _lib
 from ._lib import TNLMError

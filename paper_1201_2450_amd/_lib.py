@@ -1,7 +1,9 @@
 """ctypes loader for libtnlm.so (the HIP library built from csrc/).
 
-Argument marshalling only. If the library has not been built this module
-raises at import time: there is no CPU fallback.
+Argument marshalling only. The library is loaded on first use of `lib`
+(so that the build script can be imported from a checkout that has no
+built library yet); if it has not been built, that first use raises
+ImportError: there is no CPU fallback.
 """
 from __future__ import annotations
 
@@ -63,11 +65,26 @@ def _load():
     return lib
 
 
-lib = _load()
+_handle = None
+
+
+def get():
+    """The loaded libtnlm.so (loaded on the first call)."""
+    global _handle
+    if _handle is None:
+        _handle = _load()
+    return _handle
+
+
+def __getattr__(name):
+    # module attribute `lib`: the library, loaded on first access
+    if name == "lib":
+        return get()
+    raise AttributeError(f"module {__name__!r} has no attribute {name!r}")
 
 
 def strerror(code: int) -> str:
-    return lib.tnlm_strerror(int(code)).decode()
+    return get().tnlm_strerror(int(code)).decode()
 
 
 def check(code: int, what: str):

@@ -44,12 +44,29 @@ def _vol(t: torch.Tensor, ref: torch.Tensor | None = None) -> int:
     return t.data_ptr()
 
 
-def _f32(t: torch.Tensor | None) -> int | None:
+def _f32(t: torch.Tensor | None, shape=None, device=None) -> int | None:
     if t is None:
         return None
     if t.dtype != torch.float32 or not t.is_contiguous() or not t.is_cuda:
         raise ValueError("float32 contiguous GPU tensor expected")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"float32 tensor of shape {tuple(shape)} expected, "
+                         f"got {tuple(t.shape)}")
+    if device is not None and t.device != device:
+        raise ValueError("tensor on another device")
     return t.data_ptr()
+
+
+def _stats_shape(f: torch.Tensor):
+    """Shape of the per-voxel statistics of volumes shaped like f."""
+    return (f.shape[0], 2, 2, f.shape[1] * f.shape[2] * f.shape[3])
+
+
+def _ws_bytes(ws: torch.Tensor, f: torch.Tensor) -> int:
+    if not ws.is_cuda or ws.device != f.device or not ws.is_contiguous():
+        raise ValueError("workspace must be a contiguous tensor on the "
+                         "volumes' device")
+    return ws.numel() * ws.element_size()
 
 
 def _stream(t: torch.Tensor) -> int:
@@ -125,7 +142,7 @@ def energy(f, *, d, M, h, u=None, want_stats=False, ws=None):
         ws = _workspace(f, need)
     check(_lib.lib.tnlm_energy(ctypes.byref(geo), _DT[f.dtype], u.data_ptr(),
                                f.data_ptr(), e.data_ptr(), _f32(stats),
-                               ws.data_ptr(), ws.numel(), _stream(f)),
+                               ws.data_ptr(), _ws_bytes(ws, f), _stream(f)),
           "tnlm_energy")
     return e, stats
 
@@ -153,6 +170,8 @@ def grad(f, *, d, M, h, u=None, mode="exact", stats=None, want_f=True,
         return out
     if mode != "exact":
         raise ValueError(mode)
+    # the C ABI cannot see the statistics' extent: check it here
+    _f32(stats, _stats_shape(f), f.device)
     need = workspace_bytes(f.shape, d, M, h, _lib.OP_GRAD_EXACT)
     if stats is None:
         need += 16 * f.numel()
