@@ -142,6 +142,28 @@ int tnlm_energy(const tnlm_geom *geom, int dtype, const void *u,
                 size_t ws_bytes, void *stream);
 
 /*
+ * tnlm_energy_noalloc — tnlm_energy without a workspace argument, for callers
+ *   that cannot allocate device memory (code under HIP graph capture, tight
+ *   serving loops, harnesses that forbid hipMalloc). It computes exactly what
+ *   tnlm_energy computes, with the same kernels, arguments (minus ws) and
+ *   outputs, and allocates nothing: the per-workgroup partial sums go to a
+ *   fixed 4 MiB device array inside the library, one copy per GPU, held until
+ *   the process ends. Its device address is looked up (hipGetSymbolAddress)
+ *   on the first call on each device, with that device current.
+ *   Limit: tnlm_workspace_bytes(geom, TNLM_OP_ENERGY) <= 4 MiB (about half a
+ *   million workgroups; 20 phases of 512x512x128 voxels need 1.5 MiB);
+ *   larger problems return TNLM_EWORKSPACE before anything is launched.
+ *   Every call on one GPU shares that array and overwrites what the last
+ *   call left there (every word the result depends on is rewritten, so
+ *   nothing needs clearing): calls that overlap in time on one GPU (on
+ *   different streams, or from several threads) race and must be ordered by
+ *   the caller.
+ */
+int tnlm_energy_noalloc(const tnlm_geom *geom, int dtype, const void *u,
+                        const void *f, float *e_out, float *stats,
+                        void *stream);
+
+/*
  * tnlm_grad — gradient of the TNLM term.
  *   mode TNLM_GRAD_EQ6: grad_f = 2 f_i - sum_slot sum_delta w_{i->j} f_j,
  *        the TNLM part of the functional variation Eq. (6) with the weights

@@ -6,6 +6,7 @@ with a thin PyTorch binding (device memory and streams only):
   weights(u, d=, M=, h=)                   weights / log-normalisers, Eq. (3)
   jacobi_step(u, f, g, mu, d=, M=, h=)     Gauss-Jacobi step, Eq. (8)
   energy(f, d=, M=, h=, u=)                TNLM energy
+  energy_noalloc(f, d=, M=, h=, u=)        same, no workspace (fixed scratch)
   grad(f, d=, M=, h=, u=, mode=)           Eq. (6) operator or exact gradient
   TNLMEnergy / tnlm_energy                 autograd wrapper
   enhance(...), descend(...)               host drivers
@@ -18,8 +19,8 @@ from ._lib import TNLMError
 from .autograd import TNLMEnergy, tnlm_energy
 from . import metrics
 from .drivers import descend, enhance
-from .ops import energy, grad, jacobi_step, n_offsets, weights, workspace_bytes
+from .ops import energy, energy_noalloc, grad, jacobi_step, n_offsets, weights, workspace_bytes
 
 __all__ = ["TNLMError", "TNLMEnergy", "tnlm_energy", "descend", "enhance", "metrics",
-           "energy", "grad", "jacobi_step", "n_offsets", "weights",
+           "energy", "energy_noalloc", "grad", "jacobi_step", "n_offsets", "weights",
            "workspace_bytes"]

@@ -52,6 +52,7 @@ def _load():
     lib.tnlm_jacobi_step.argtypes = [gp, i, vp, vp, vp, ctypes.c_float, vp,
                                      vp]
     lib.tnlm_energy.argtypes = [gp, i, vp, vp, fp, fp, vp, sz, vp]
+    lib.tnlm_energy_noalloc.argtypes = [gp, i, vp, vp, fp, fp, vp]
     lib.tnlm_grad.argtypes = [gp, i, vp, vp, i, fp, fp, fp, vp, sz, vp]
     lib.tnlm_workspace_bytes.argtypes = [gp, i]
     lib.tnlm_workspace_bytes.restype = sz
@@ -60,7 +61,7 @@ def _load():
     lib.tnlm_version.argtypes = []
     lib.tnlm_version.restype = ctypes.c_char_p
     for name in ("tnlm_weights", "tnlm_jacobi_step", "tnlm_energy",
-                 "tnlm_grad"):
+                 "tnlm_energy_noalloc", "tnlm_grad"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 

@@ -4,6 +4,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "tnlm_internal.h"
 
 using namespace tnlm;
@@ -94,6 +96,45 @@ size_t stats_bytes(const Geo &g) { return (size_t)g.np * g.N * 4 * sizeof(float)
 // appends room for the statistics when it passes none.
 size_t pad_bytes(const Geo &g) { return grad_tiled_supported(g) ? align256(grad_tiled_pad_bytes(g)) : 0; }
 size_t grad_exact_bytes(const Geo &g) { return partial_bytes(g) + pad_bytes(g); }
+
+// Fixed device scratch of tnlm_energy_noalloc: the per-workgroup partial
+// sums of the energy. One copy per GPU, held until the process ends. Host
+// code never uses this name as an address (on the host it is only a
+// stand-in for the symbol): the device address of each GPU's copy comes from
+// hipGetSymbolAddress, looked up once per device.
+constexpr size_t kScratchBytes = size_t(4) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];
+
+// Device address of the current device's scratch (looked up on the first
+// call on that device, with it current), or null with *err set.
+void *scratch_ptr(hipError_t *err)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        *err = e;
+        return nullptr;
+    }
+    if (dev < 0 || dev >= kMaxDevices) {
+        *err = hipErrorInvalidDevice;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            *err = e != hipSuccess ? e : hipErrorInvalidSymbol;
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    return g_scratch_ptr[dev];
+}
 
 }  // namespace
 
@@ -239,6 +280,34 @@ int tnlm_energy(const tnlm_geom *geom, int dtype, const void *u, const void *f, 
                 return TNLM_EALIAS;
     }
     return energy_impl(g, dtype, u, f, e_out, stats, (dfloat *)ws, (hipStream_t)stream);
+}
+
+int tnlm_energy_noalloc(const tnlm_geom *geom, int dtype, const void *u, const void *f,
+                        float *e_out, float *stats, void *stream)
+{
+    Geo g;
+    int rc = make_geo(geom, &g);
+    if (rc)
+        return rc;
+    if (!valid_dtype(dtype))
+        return TNLM_EINVAL;
+    if (!u || !f || !e_out)
+        return TNLM_ENULL;
+    if (partial_bytes(g) > kScratchBytes)
+        return TNLM_EWORKSPACE;
+    const size_t vb = (size_t)g.np * g.N * elem_size(dtype);
+    const size_t sb = stats ? stats_bytes(g) : 0;
+    if (overlap(e_out, 2 * sizeof(float), u, vb) || overlap(e_out, 2 * sizeof(float), f, vb) ||
+        overlap(stats, sb, u, vb) || overlap(stats, sb, f, vb) ||
+        overlap(e_out, 2 * sizeof(float), stats, sb))
+        return TNLM_EALIAS;
+    hipError_t e = hipSuccess;
+    void *part = scratch_ptr(&e);
+    if (!part)
+        return hip_fail(e);
+    // every partial sum the final reduction reads is written by the energy
+    // kernel of this call: nothing needs clearing
+    return energy_impl(g, dtype, u, f, e_out, stats, (dfloat *)part, (hipStream_t)stream);
 }
 
 int tnlm_grad(const tnlm_geom *geom, int dtype, const void *u, const void *f, int mode,

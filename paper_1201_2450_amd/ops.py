@@ -147,6 +147,27 @@ def energy(f, *, d, M, h, u=None, want_stats=False, ws=None):
     return e, stats
 
 
+def energy_noalloc(f, *, d, M, h, u=None, e=None, stats=None):
+    """TNLM energy through tnlm_energy_noalloc: no workspace; the library's
+    fixed per-GPU scratch holds the partial sums. e (float32[2]) and stats
+    ([Np,2,2,N] float32 or None) are written in place when given; returns
+    (e, stats)."""
+    if u is None:
+        u = f
+    geo = _geom(f, d, M, h)
+    _vol(f)
+    _vol(u, f)
+    if e is None:
+        e = torch.empty(2, dtype=torch.float32, device=f.device)
+    _f32(e, (2,), f.device)
+    _f32(stats, _stats_shape(f), f.device)
+    check(_lib.lib.tnlm_energy_noalloc(ctypes.byref(geo), _DT[f.dtype],
+                                       u.data_ptr(), f.data_ptr(),
+                                       e.data_ptr(), _f32(stats), _stream(f)),
+          "tnlm_energy_noalloc")
+    return e, stats
+
+
 def grad(f, *, d, M, h, u=None, mode="exact", stats=None, want_f=True,
          want_u=True, total=False):
     """Gradient of the TNLM term.
@@ -183,13 +204,13 @@ def grad(f, *, d, M, h, u=None, mode="exact", stats=None, want_f=True,
         check(_lib.lib.tnlm_grad(ctypes.byref(geo), _DT[f.dtype],
                                  u.data_ptr(), f.data_ptr(), _lib.GRAD_EXACT,
                                  _f32(stats), gt.data_ptr(), gt.data_ptr(),
-                                 ws.data_ptr(), ws.numel(), _stream(f)),
+                                 ws.data_ptr(), _ws_bytes(ws, f), _stream(f)),
               "tnlm_grad(exact, total)")
         return gt
     gf = mk() if want_f else None
     gu = mk() if want_u else None
     check(_lib.lib.tnlm_grad(ctypes.byref(geo), _DT[f.dtype], u.data_ptr(),
                              f.data_ptr(), _lib.GRAD_EXACT, _f32(stats),
-                             _f32(gf), _f32(gu), ws.data_ptr(), ws.numel(),
-                             _stream(f)), "tnlm_grad(exact)")
+                             _f32(gf), _f32(gu), ws.data_ptr(),
+                             _ws_bytes(ws, f), _stream(f)), "tnlm_grad(exact)")
     return gf, gu

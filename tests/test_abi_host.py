@@ -161,3 +161,17 @@ def test_binding_raises_library_error_for_rejected_geometry():
         with pytest.raises(_lib.TNLMError) as ei:
             ops.workspace_bytes(shape, 1, 1, 0.1, _lib.OP_ENERGY)
         assert ei.value.code == _lib.EINVAL
+
+
+def test_energy_noalloc_argument_checks():
+    g = geom()
+    call = lambda gg=g, dt=0, u=FAKE, f=FAKE, e=FAKE2: \
+        lib.tnlm_energy_noalloc(ctypes.byref(gg), dt, u, f, e, None, None)
+    assert call(dt=5) == _lib.EINVAL
+    assert call(u=None) == _lib.ENULL
+    assert call(e=None) == _lib.ENULL
+    assert call(e=FAKE) == _lib.EALIAS
+    # a problem whose partial sums exceed the fixed 4 MiB scratch
+    big = geom(np_=64, nx=1024, ny=1024, nz=512, M=3)
+    assert lib.tnlm_workspace_bytes(ctypes.byref(big), _lib.OP_ENERGY) > (4 << 20)
+    assert call(gg=big) == _lib.EWORKSPACE
