@@ -64,6 +64,10 @@ def _L():
                                            ctypes.c_int64, ctypes.c_int64,
                                            ctypes.c_int64]
         lib.tnlmo_local_energy.restype = ctypes.c_double
+        lib.tnlmo_error_model.argtypes = [g, dp, dp] + [ctypes.c_double] * 4 \
+            + [dp] * 11
+        lib.tnlmo_error_model_at.argtypes = [g, dp, dp] \
+            + [ctypes.c_double] * 4 + [ip, ctypes.c_int64] + [dp] * 7
         _lib = lib
     return _lib
 
@@ -182,3 +186,43 @@ def local_energy(u, f, d, M, h, k, x, y, z):
     u, f = _vol(u), _vol(f)
     g = _geom(u.shape, d, M, h)
     return _L().tnlmo_local_energy(ctypes.byref(g), _dp(u), _dp(f), k, x, y, z)
+
+
+
+def error_model(u, f, d, M, h, depth, ulp, lam, corr, grad=False):
+    """First-order rounding-error model of an FP32 evaluation whose distance
+    sums pass every term through at most `depth` roundings of unit roundoff
+    `ulp` (see tnlm_oracle.c): for each output the variance proxy V of the independent
+    roundings and the coefficient sum D of the correlated one, so that the
+    error is at most lam*sqrt(V) + corr*|D| (corr = bound of the relative
+    error of 1/(2h^2)). Returns a dict of float64 arrays: lse_v, lse_d,
+    nb_v, nb_d, e_v, e_d ([Np, 2, N]), w_b ([Np, 2, N], already combined) and,
+    with grad=True, gf_v, gf_d, gu_v, gu_d ([Np, Nx, Ny, Nz]; a
+    single-threaded scatter, small grids only)."""
+    u, f = _vol(u), _vol(f)
+    g = _geom(u.shape, d, M, h)
+    N = int(np.prod(u.shape[1:]))
+    keys = ("lse_v", "lse_d", "w_b", "nb_v", "nb_d", "e_v", "e_d")
+    out = {k: np.empty((u.shape[0], 2, N)) for k in keys}
+    gkeys = ("gf_v", "gf_d", "gu_v", "gu_d")
+    if grad:
+        out.update({k: np.empty(u.shape) for k in gkeys})
+    _L().tnlmo_error_model(ctypes.byref(g), _dp(u), _dp(f), float(depth),
+                           float(ulp), float(lam), float(corr),
+                           *[_dp(out[k]) for k in keys],
+                           *[_dp(out.get(k)) for k in gkeys])
+    return out
+
+
+def error_model_at(u, f, d, M, h, depth, ulp, lam, corr, idx):
+    """The per-voxel outputs of error_model at flat indices idx: lse_v,
+    lse_d, w_b, nb_v, nb_d, e_v, e_d, each [len(idx), 2]."""
+    u, f = _vol(u), _vol(f)
+    g = _geom(u.shape, d, M, h)
+    idx = _idx(idx)
+    keys = ("lse_v", "lse_d", "w_b", "nb_v", "nb_d", "e_v", "e_d")
+    out = {k: np.empty((idx.shape[0], 2)) for k in keys}
+    _L().tnlmo_error_model_at(ctypes.byref(g), _dp(u), _dp(f), float(depth),
+                              float(ulp), float(lam), float(corr), _ip(idx),
+                              idx.shape[0], *[_dp(out[k]) for k in keys])
+    return out

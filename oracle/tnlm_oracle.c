@@ -607,3 +607,426 @@ double tnlmo_local_energy(const ogeom *g, const double *u, const double *f,
     free(terms);
     return E;
 }
+
+/* ------------------------------------------------------------------------ */
+/* First-order rounding-error model of a single-precision evaluation.       */
+/*                                                                          */
+/* Tolerance infrastructure for the parity tests (how far an FP32           */
+/* evaluation of the definitions above can be expected to land from them),  */
+/* not part of the method.                                                  */
+/*                                                                          */
+/* Sources. The exponent a_k = D_k/(2h^2) of candidate k of one voxel and   */
+/* direction (a "block") is computed with an error da_k = eta * a_k + t_k.  */
+/* eta, the relative error of the constant 1/(2h^2), is one value for the   */
+/* whole evaluation (fully correlated). t_k collects roundings modelled as  */
+/* independent, mean zero and bounded (the probabilistic rounding model of  */
+/* Higham and Mary, 2019), each of at most one unit roundoff ulp of the     */
+/* value it rounds:                                                         */
+/*   - the distance, a sum of positive terms: a rounding of partial sum s   */
+/*     moves D by at most ulp*s; with every term passing through at most    */
+/*     `depth` roundings, sum_r s_r^2 <= depth * D^2, and the rounding of   */
+/*     each difference adds at most (2 ulp)^2 D^2 in all;                   */
+/*   - the shifted exponent, one rounding of at most a_k + a_0 + 70 (shifts */
+/*     start from a_0, the exponent of the zero offset, or from the         */
+/*     log-normaliser, lowered by at most 69.3 = 100 ln 2);                 */
+/*   - the exponential, about two units of its result.                      */
+/* So t_k is a sum of independent bounded terms whose bounds have the       */
+/* square sum tb_k^2 = ulp^2 [(depth + 4) a_k^2 + (a_k + a_0 + 70)^2 + 4].  */
+/* There is one such set for each kernel that recomputes the distances:     */
+/* the forward kernels (F) and the adjoint (A), which reads the forward     */
+/* pass's log-normalisers and e.                                            */
+/*                                                                          */
+/* Propagation. Every output is, to first order, X = sum_src c_src da_src   */
+/* (plus, for dE/du, eta times the output itself: its terms carry the       */
+/* factor 1/(8h^2), which scales with 1/(2h^2)).                            */
+/* This returns for each output the variance proxy V = sum c^2 tb^2 of the  */
+/* independent part and the coefficient sum D = sum c a of the correlated   */
+/* one, so that |X| <= lam sqrt(V) + |eta| |D| except with probability at   */
+/* most 2 exp(-lam^2/2) (Hoeffding's inequality over the elementary         */
+/* roundings).                                                              */
+/*                                                                          */
+/* Coefficients, with w_k the normalised weights, cbar = sum w c:           */
+/*   forward averages sum_k w_k c_k:  c_k = -w_k (c_k - cbar)                */
+/*   log-normaliser:                  c_k = -w_k                             */
+/*   weight w_k:                      c_m = w_k (w_m - [m = k])              */
+/* The adjoint evaluates w_k = exp(-a_k - L) with the forward L and e, so   */
+/* dw_k = w_k (-dA_k + sum_m w_m dF_m) and, for Dbar_k = -(w_k/(8h^2))      */
+/* (r_k^2 - e), dDbar_k = -(w_k/(8h^2)) [-dA_k (r_k^2 - e)                   */
+/*                        + sum_m w_m dF_m (r_k^2 + r_m^2 - 2e)].            */
+/*                                                                          */
+/* Outputs (each nullable):                                                 */
+/*   lse_v, lse_d [np][2][N]  log-normaliser (V, D)                         */
+/*   w_b          [np][2][N]  max over offsets of lam sqrt(V) + corr |D| of  */
+/*                            the weights of the voxel                      */
+/*   nb_v, nb_d   [np][2][N]  sum_delta w f_j (neighbour average, Eq. (8))  */
+/*   e_v, e_d     [np][2][N]  e = sum_delta w r^2                           */
+/*   gf_v, gf_d, gu_v, gu_d [np][N]  the two parts of the exact gradient    */
+/*                            (scatter form over blocks, single-threaded)   */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int64_t n;          /* valid candidates */
+    double a0, ebar, rbar;
+    double *a, *tb, *w, *c; /* [W] in offset order over valid candidates */
+} oblock;
+
+static void block_eval(const ogeom *g, const double *u, const double *f, double depth, double ulp,
+                       int64_t i, int slot, int64_t x, int64_t y, int64_t z, oblock *b)
+{
+    const int64_t j = neighbour(g, i, slot);
+    const double inv2h2 = 1.0 / (2.0 * g->h * g->h);
+    const double fi = f ? f[vidx(g, i, x, y, z)] : 0.0;
+    b->a0 = patch_dist(g, u, i, j, x, y, z, 0, 0, 0) * inv2h2;
+    int64_t n = 0;
+    double amin = INFINITY;
+    for (int64_t ox = -g->M; ox <= g->M; ++ox)
+        for (int64_t oy = -g->M; oy <= g->M; ++oy)
+            for (int64_t oz = -g->M; oz <= g->M; ++oz) {
+                if (!inside(g, x + ox, y + oy, z + oz))
+                    continue;
+                b->a[n] = patch_dist(g, u, i, j, x, y, z, ox, oy, oz) * inv2h2;
+                b->c[n] = f ? f[vidx(g, j, x + ox, y + oy, z + oz)] : 0.0;
+                if (b->a[n] < amin)
+                    amin = b->a[n];
+                ++n;
+            }
+    double Z = 0.0;
+    for (int64_t k = 0; k < n; ++k) {
+        b->w[k] = exp(-(b->a[k] - amin));
+        Z += b->w[k];
+    }
+    double eb = 0.0, rb = 0.0;
+    for (int64_t k = 0; k < n; ++k) {
+        b->w[k] /= Z;
+        const double t = b->a[k] + b->a0 + 70.0;
+        b->tb[k] = ulp * sqrt((depth + 4.0) * b->a[k] * b->a[k] + t * t + 4.0);
+        const double r = fi - b->c[k];
+        eb += b->w[k] * r * r;
+        rb += b->w[k] * r;
+    }
+    b->n = n;
+    b->ebar = eb;
+    b->rbar = rb;
+}
+
+/* V and D of a forward average sum_k w_k c_k (c = the block's f_j values, or
+ * r^2 with fi given). */
+static void fwd_avg(const oblock *b, int r2mode, double fi, double *V, double *D)
+{
+    double cb = 0.0;
+    for (int64_t k = 0; k < b->n; ++k) {
+        const double c = r2mode ? (fi - b->c[k]) * (fi - b->c[k]) : b->c[k];
+        cb += b->w[k] * c;
+    }
+    double v = 0.0, d = 0.0;
+    for (int64_t k = 0; k < b->n; ++k) {
+        const double c = r2mode ? (fi - b->c[k]) * (fi - b->c[k]) : b->c[k];
+        const double co = -b->w[k] * (c - cb);
+        v += co * co * b->tb[k] * b->tb[k];
+        d += co * b->a[k];
+    }
+    *V = v;
+    *D = d;
+}
+
+/* Per-voxel outputs of the model for one voxel (flat index) and direction,
+ * written at offset o of each non-null output. */
+static void voxel_model(const ogeom *g, const double *u, const double *f, double depth,
+                        double ulp, double lam, double corr, int64_t flat, int slot, oblock *bp,
+                        int64_t o, double *lse_v, double *lse_d, double *w_b, double *nb_v,
+                        double *nb_d, double *e_v, double *e_d)
+{
+    const int64_t S = 2 * g->M + 1, W = S * S * S;
+    int64_t i, x, y, z;
+    unflatten(g, flat, &i, &x, &y, &z);
+    const double fi = f ? f[flat] : 0.0;
+    oblock b = *bp;
+    block_eval(g, u, f, depth, ulp, i, slot, x, y, z, &b);
+    double V, D;
+    if (lse_v || lse_d) {
+        V = 0.0;
+        D = 0.0;
+        double wa = 0.0;
+        for (int64_t k = 0; k < b.n; ++k) {
+            V += b.w[k] * b.w[k] * b.tb[k] * b.tb[k];
+            D -= b.w[k] * b.a[k];
+            wa += b.w[k] * b.a[k];
+        }
+        /* the log of the sum and the removal of the shift: two roundings
+         * relative to about a_0 + log W */
+        const double lz = ulp * (2.0 * b.a0 + 2.0 * log((double)W) + wa);
+        V += lz * lz;
+        if (lse_v)
+            lse_v[o] = V;
+        if (lse_d)
+            lse_d[o] = D;
+    }
+    if (w_b) {
+        double s2 = 0.0, sa = 0.0, best = 0.0;
+        for (int64_t k = 0; k < b.n; ++k) {
+            s2 += b.w[k] * b.w[k] * b.tb[k] * b.tb[k];
+            sa += b.w[k] * b.a[k];
+        }
+        for (int64_t k = 0; k < b.n; ++k) {
+            const double wk = b.w[k], tk = b.tb[k];
+            /* sum_m (w_k (w_m - [m=k]))^2 tb_m^2 */
+            const double Vk = wk * wk * (s2 - wk * wk * tk * tk + (wk - 1.0) * (wk - 1.0) * tk * tk);
+            const double Dk = wk * (sa - b.a[k]);
+            const double bk = lam * sqrt(Vk) + corr * fabs(Dk);
+            if (bk > best)
+                best = bk;
+        }
+        w_b[o] = best;
+    }
+    if (nb_v || nb_d) {
+        fwd_avg(&b, 0, fi, &V, &D);
+        if (nb_v)
+            nb_v[o] = V;
+        if (nb_d)
+            nb_d[o] = D;
+    }
+    if (e_v || e_d) {
+        fwd_avg(&b, 1, fi, &V, &D);
+        if (e_v)
+            e_v[o] = V;
+        if (e_d)
+            e_d[o] = D;
+    }
+}
+
+/* The per-voxel outputs of tnlmo_error_model at flat indices idx[0..n):
+ * each output [n][2] (direction slot fastest). */
+void tnlmo_error_model_at(const ogeom *g, const double *u, const double *f, double depth,
+                          double ulp, double lam, double corr, const int64_t *idx, int64_t n,
+                          double *lse_v, double *lse_d, double *w_b, double *nb_v, double *nb_d,
+                          double *e_v, double *e_d)
+{
+    const int64_t S = 2 * g->M + 1, W = S * S * S;
+#pragma omp parallel
+    {
+        oblock bl;
+        double *mem = (double *)malloc(sizeof(double) * 4 * W);
+        bl.a = mem;
+        bl.tb = mem + W;
+        bl.w = mem + 2 * W;
+        bl.c = mem + 3 * W;
+#pragma omp for schedule(dynamic, 4)
+        for (int64_t t = 0; t < n; ++t) {
+            if (!mem)
+                continue;
+            for (int slot = 0; slot < 2; ++slot)
+                voxel_model(g, u, f, depth, ulp, lam, corr, idx[t], slot, &bl, t * 2 + slot,
+                            lse_v, lse_d, w_b, nb_v, nb_d, e_v, e_d);
+        }
+        free(mem);
+    }
+}
+
+/* Scatter of one block's gradient-error terms (see above) into the
+ * accumulators gfv, gfd, guv, gud ([np][N] each). mem: 4W + 2 ni + 2 nj +
+ * 2 ni doubles of scratch, touched: ni + nj bytes (ni = (2d+1)^3,
+ * nj = (2(M+d)+1)^3). */
+static void block_scatter(const ogeom *g, const double *u, const double *f, double depth,
+                          double ulp, int64_t i, int slot, int64_t x, int64_t y, int64_t z,
+                          double *mem, unsigned char *touched, int want_f, int want_u,
+                          double *gfv, double *gfd, double *guv, double *gud)
+{
+    const int64_t S = 2 * g->M + 1, W = S * S * S;
+    const int64_t Li = 2 * g->d + 1, Lj = 2 * (g->M + g->d) + 1;
+    const int64_t ni = Li * Li * Li, nj = Lj * Lj * Lj;
+    oblock b;
+    b.a = mem;
+    b.tb = mem + W;
+    b.w = mem + 2 * W;
+    b.c = mem + 3 * W;
+    /* P0 = sum_k w_k G_k(q), P1 = sum_k w_k (r_k^2 - e) G_k(q) for the
+     * outputs q the block touches: phase i within d of v, phase j within
+     * M+d of v (clamped coordinates, so clamped copies merge) */
+    double *P0i = mem + 4 * W, *P1i = P0i + ni, *P0j = P1i + ni, *P1j = P0j + nj;
+    int64_t *lq = (int64_t *)(P1j + nj); /* per (k, side): (output, G) pairs */
+    double *lG = (double *)(lq + ni);
+    const double k8 = 1.0 / (8.0 * g->h * g->h);
+    const int64_t j = neighbour(g, i, slot);
+    block_eval(g, u, f, depth, ulp, i, slot, x, y, z, &b);
+    const int64_t vi = vidx(g, i, x, y, z);
+    const double fi = f[vi], e = b.ebar;
+    /* per-block sums over the F sources */
+    double S0 = 0.0, S1 = 0.0, S2 = 0.0, T0 = 0.0, T1 = 0.0;
+    for (int64_t m = 0; m < b.n; ++m) {
+        const double rm = fi - b.c[m], q2 = rm * rm - e;
+        const double wt = b.w[m] * b.w[m] * b.tb[m] * b.tb[m];
+        S0 += wt;
+        S1 += wt * q2;
+        S2 += wt * q2 * q2;
+        T0 += b.w[m] * b.a[m];
+        T1 += b.w[m] * b.a[m] * q2;
+    }
+    /* image part, self: X = 1/2 sum_k w_k r_k (-dA_k + sum_m w_m dF_m) */
+    if (want_f) {
+        double v = 0.25 * b.rbar * b.rbar * S0, d = 0.0;
+        for (int64_t k = 0; k < b.n; ++k) {
+            const double r = fi - b.c[k];
+            v += 0.25 * b.w[k] * b.w[k] * r * r * b.tb[k] * b.tb[k];
+            d += -0.5 * b.w[k] * r * b.a[k] + 0.5 * b.w[k] * r * T0;
+        }
+        gfv[vi] += v;
+        gfd[vi] += d;
+    }
+    memset(touched, 0, (size_t)(ni + nj));
+    int64_t k = 0;
+    for (int64_t ox = -g->M; ox <= g->M; ++ox)
+        for (int64_t oy = -g->M; oy <= g->M; ++oy)
+            for (int64_t oz = -g->M; oz <= g->M; ++oz) {
+                if (!inside(g, x + ox, y + oy, z + oz))
+                    continue;
+                const double wk = b.w[k], r = fi - b.c[k];
+                const double q2 = r * r - e, tk = b.tb[k], ak = b.a[k];
+                ++k;
+                /* image part, other, to (j, v+delta):
+                 * X = -1/2 w_k r (-dA_k + sum_m w_m dF_m) */
+                if (want_f) {
+                    const int64_t qo = vidx(g, j, x + ox, y + oy, z + oz);
+                    gfv[qo] += 0.25 * wk * wk * r * r * (tk * tk + S0);
+                    gfd[qo] += 0.5 * wk * r * ak - 0.5 * wk * r * T0;
+                }
+                if (!want_u)
+                    continue;
+                /* weight part: +2 Delta dDbar_k to clamp(v+p) (phase i) and
+                 * -2 Delta dDbar_k to clamp(v+delta+p) (phase j) */
+                for (int side = 0; side < 2; ++side) {
+                    const int64_t L = side == 0 ? Li : Lj;
+                    const int64_t R = side == 0 ? g->d : g->M + g->d;
+                    int64_t nl = 0;
+                    for (int64_t px = -g->d; px <= g->d; ++px)
+                        for (int64_t py = -g->d; py <= g->d; ++py)
+                            for (int64_t pz = -g->d; pz <= g->d; ++pz) {
+                                const int64_t ax = x + px, ay = y + py, az = z + pz;
+                                const int64_t bx = ax + ox, by = ay + oy, bz = az + oz;
+                                const double Delta = ext(g, u, i, ax, ay, az) - ext(g, u, j, bx, by, bz);
+                                const int64_t cx = clampi(side == 0 ? ax : bx, 0, g->nx - 1);
+                                const int64_t cy = clampi(side == 0 ? ay : by, 0, g->ny - 1);
+                                const int64_t cz = clampi(side == 0 ? az : bz, 0, g->nz - 1);
+                                const int64_t l = ((cx - x + R) * L + (cy - y + R)) * L + (cz - z + R);
+                                int64_t t = 0;
+                                while (t < nl && lq[t] != l)
+                                    ++t;
+                                if (t == nl) {
+                                    lq[nl] = l;
+                                    lG[nl] = 0.0;
+                                    ++nl;
+                                }
+                                lG[t] += (side == 0 ? 2.0 : -2.0) * Delta;
+                            }
+                    double *P0 = side == 0 ? P0i : P0j, *P1 = side == 0 ? P1i : P1j;
+                    unsigned char *tch = side == 0 ? touched : touched + ni;
+                    const int64_t ph = side == 0 ? i : j;
+                    for (int64_t t = 0; t < nl; ++t) {
+                        const int64_t l = lq[t];
+                        if (!tch[l]) {
+                            tch[l] = 1;
+                            P0[l] = 0.0;
+                            P1[l] = 0.0;
+                        }
+                        P0[l] += wk * lG[t];
+                        P1[l] += wk * q2 * lG[t];
+                        const int64_t lz = l % L, ly = (l / L) % L, lx = l / (L * L);
+                        const int64_t q = vidx(g, ph, x - R + lx, y - R + ly, z - R + lz);
+                        const double ca = k8 * wk * q2 * lG[t]; /* coefficient of dA_k */
+                        guv[q] += ca * ca * tk * tk;
+                        /* correlated: through a_k, and through the factor
+                         * 1/(8h^2) of the term itself (-ca), which scales
+                         * with 1/(2h^2) */
+                        gud[q] += ca * ak - ca;
+                    }
+                }
+            }
+    if (!want_u)
+        return;
+    /* F part of every touched output: coefficient of dF_m is
+     * -k8 w_m (P1 + (r_m^2 - e) P0) */
+    for (int side = 0; side < 2; ++side) {
+        const int64_t n = side == 0 ? ni : nj, L = side == 0 ? Li : Lj;
+        const int64_t R = side == 0 ? g->d : g->M + g->d;
+        const unsigned char *tch = side == 0 ? touched : touched + ni;
+        const double *P0 = side == 0 ? P0i : P0j, *P1 = side == 0 ? P1i : P1j;
+        const int64_t ph = side == 0 ? i : j;
+        for (int64_t l = 0; l < n; ++l) {
+            if (!tch[l])
+                continue;
+            const int64_t lz = l % L, ly = (l / L) % L, lx = l / (L * L);
+            const int64_t q = vidx(g, ph, x - R + lx, y - R + ly, z - R + lz);
+            guv[q] += k8 * k8 * (P1[l] * P1[l] * S0 + 2.0 * P1[l] * P0[l] * S1 + P0[l] * P0[l] * S2);
+            gud[q] += -k8 * (P1[l] * T0 + P0[l] * T1);
+        }
+    }
+}
+
+void tnlmo_error_model(const ogeom *g, const double *u, const double *f, double depth, double ulp,
+                       double lam, double corr, double *lse_v, double *lse_d, double *w_b,
+                       double *nb_v, double *nb_d, double *e_v, double *e_d, double *gf_v,
+                       double *gf_d, double *gu_v, double *gu_d)
+{
+    const int64_t N = nvox_phase(g);
+    const int64_t S = 2 * g->M + 1, W = S * S * S;
+    if (lse_v || lse_d || w_b || nb_v || nb_d || e_v || e_d) {
+#pragma omp parallel
+        {
+            oblock bl;
+            double *mem = (double *)malloc(sizeof(double) * 4 * W);
+            bl.a = mem;
+            bl.tb = mem + W;
+            bl.w = mem + 2 * W;
+            bl.c = mem + 3 * W;
+#pragma omp for schedule(dynamic, 64)
+            for (int64_t flat = 0; flat < g->np * N; ++flat) {
+                if (!mem)
+                    continue;
+                const int64_t i = flat / N, v = flat - i * N;
+                for (int slot = 0; slot < 2; ++slot)
+                    voxel_model(g, u, f, depth, ulp, lam, corr, flat, slot, &bl,
+                                (i * 2 + slot) * N + v, lse_v, lse_d, w_b, nb_v, nb_d, e_v, e_d);
+            }
+            free(mem);
+        }
+    }
+    if (!(gf_v || gf_d || gu_v || gu_d))
+        return;
+    const int64_t tot = g->np * N;
+    double *outs[4] = {gf_v, gf_d, gu_v, gu_d};
+    for (int q = 0; q < 4; ++q)
+        if (outs[q])
+            memset(outs[q], 0, sizeof(double) * tot);
+    /* blocks in parallel, each thread scattering into private copies that
+     * are added up at the end */
+#pragma omp parallel
+    {
+        double *acc = (double *)calloc((size_t)(4 * tot), sizeof(double));
+        const int64_t Li = 2 * g->d + 1, Lj = 2 * (g->M + g->d) + 1;
+        const int64_t ni = Li * Li * Li, nj = Lj * Lj * Lj;
+        double *mem = (double *)malloc(sizeof(double) * (4 * W + 2 * ni + 2 * nj + 2 * ni));
+        unsigned char *touched = (unsigned char *)calloc((size_t)(ni + nj), 1);
+        const int ok = acc && mem && touched;
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t flat = 0; flat < tot; ++flat) {
+            if (!ok)
+                continue;
+            int64_t i, x, y, z;
+            unflatten(g, flat, &i, &x, &y, &z);
+            for (int slot = 0; slot < 2; ++slot)
+                block_scatter(g, u, f, depth, ulp, i, slot, x, y, z, mem, touched,
+                              gf_v || gf_d, gu_v || gu_d, acc, acc + tot, acc + 2 * tot,
+                              acc + 3 * tot);
+        }
+#pragma omp critical
+        {
+            if (ok)
+                for (int q = 0; q < 4; ++q)
+                    if (outs[q])
+                        for (int64_t t = 0; t < tot; ++t)
+                            outs[q][t] += acc[q * tot + t];
+        }
+        free(acc);
+        free(mem);
+        free(touched);
+    }
+}

@@ -4,22 +4,103 @@ import sys
 import numpy as np
 import torch
 
+from oracle import oracle
 from phantom import quantise, random_volumes, scaled_phantom
 
 TORCH_DT = {"f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}
 # half a unit in the last place, relative, of each storage format
 STORE_EPS = {"f32": 0.0, "bf16": 2.0 ** -8, "f16": 2.0 ** -11}
-FP32_TOL = 1e-5  # normwise relative tolerance of FP32 outputs vs the oracle
-# Stress inputs (uniform noise with h far below the data range) push the
-# weight exponent c2*D = D*log2(e)/(2h^2) to ~300 for the candidates that
-# matter; FP32 rounding of the 27-term distance D (about sqrt(27)*2^-24
-# relative) then moves each exponent by ~1e-5, so weights and everything
-# built from them carry ~1e-5..1e-4 relative error before any kernel error.
-STRESS_TOL = 1e-4
+# Tolerances. Every FP32 output is compared normwise (max |x - ref| / max
+# |ref|) with the FP64 oracle on identical inputs, at
+#   tol = max(FP32_TOL, max(bound) / max|ref|),
+# where bound is the first-order rounding-error bound of oracle.error_model
+# for that case and output (the patch distances' rounding amplified by the
+# weight exponents, which reach c2*D ~ 300 on steep inputs): FP32_TOL is the
+# target wherever the conditioning allows it, the derived bound where it
+# does not.
+FP32_TOL = 1e-5
+U32 = 2.0 ** -24   # unit roundoff of FP32
+LAM = 6.0          # Hoeffding factor: each bound fails with prob <= 2 e^-18
+CORR = 3 * U32     # relative error of 1/(2h^2): h rounded to FP32, then the constant
 
 
-def tol_for(kind):
-    return STRESS_TOL if kind == "uniform" else FP32_TOL
+def tiled(d, M):
+    """Geometries the LDS-tiled kernels take (patch 3^3, window up to 11^3)."""
+    return d == 1 and 1 <= M <= 5
+
+
+def depth(d, M, generic=False):
+    """Roundings a squared difference passes through in the kernels'
+    distance sums: the tiled kernels take three separable 3-tap sums (the
+    z sum with the squares fused, 3; x, 2; y, 2), the one-thread kernels a
+    running sum over the (2d+1)^3 patch."""
+    return 7 if tiled(d, M) and not generic else (2 * d + 1) ** 3
+
+
+class Bounds:
+    """Per-element FP32 error bounds of one case (oracle.error_model). With
+    idx, only the per-voxel outputs at those flat indices (error_model_at)."""
+
+    def __init__(self, u64, f64, d, M, h, grad=False, idx=None):
+        self.args = (u64, f64, d, M, h)
+        self.shape = u64.shape
+        self.N = int(np.prod(self.shape[1:]))
+        self.idx = idx
+        if idx is None:
+            self.m = oracle.error_model(u64, f64, d, M, h, depth(d, M), U32,
+                                        LAM, CORR, grad=grad)
+        else:
+            self.m = oracle.error_model_at(u64, f64, d, M, h, depth(d, M),
+                                           U32, LAM, CORR, idx)
+
+    def _b(self, v, dd):
+        return LAM * np.sqrt(v) + CORR * np.abs(dd)
+
+    def _dirs(self, key):
+        # [Np, 2, N] whole grid, or [n, 2] sampled
+        return self.m[key + "_v"], self.m[key + "_d"]
+
+    def lse(self):
+        return self._b(*self._dirs("lse"))
+
+    def e(self):
+        return self._b(*self._dirs("e"))
+
+    def stats(self):
+        # [Np, 2, 2, N] whole grid, [n, 2, 2] sampled (as the oracle's stats)
+        return np.stack([self.lse(), self.e()], axis=2)
+
+    def _both(self, key):
+        v, dd = self._dirs(key)
+        b = self._b(v.sum(axis=1), dd.sum(axis=1))
+        return b.reshape(self.shape) if self.idx is None else b
+
+    def jacobi(self, mu):
+        return self._both("nb") / (2.0 + mu)
+
+    def eq6(self):
+        return self._both("nb")
+
+    def energy(self):
+        return LAM * np.sqrt(self.m["e_v"].sum() / 16.0) + \
+            CORR * abs(self.m["e_d"].sum() / 4.0)
+
+    def w(self):
+        """Bound of every weight of a voxel and direction, [Np, 2, 1, N]
+        (the full weight tensor comes from the one-thread kernels)."""
+        u64, f64, d, M, h = self.args
+        m = oracle.error_model(u64, f64, d, M, h, depth(d, M, generic=True),
+                               U32, LAM, CORR)
+        return m["w_b"][:, :, None, :]
+
+    def gf(self):
+        return self._b(self.m["gf_v"], self.m["gf_d"])
+
+    def gu(self):
+        return self._b(self.m["gu_v"], self.m["gu_d"])
+
+    def total(self):
+        return self.gf() + self.gu()
 
 
 def say(*a):
@@ -69,33 +150,29 @@ def with_peaks(idx, *fields):
     return np.array(sorted(set(int(i) for i in idx) | extra), dtype=np.int64)
 
 
-def assert_close(got, ref, tol, what):
-    e = normwise(got, ref)
-    say(f"  {what}: normwise rel err {e:.3e} (tol {tol:.1e})")
-    assert np.isfinite(np.asarray(got)).all(), f"{what}: non-finite output"
-    assert e <= tol, f"{what}: normwise rel err {e:.3e} > {tol:.1e}"
-
-
-def assert_close_faces(got, ref, idx, shape, what):
-    """The weight part of the exact gradient, dE/du, at flat indices idx:
-    FP32_TOL inside the grid and 2 FP32_TOL on its faces, where the
-    derivatives of the clamped copies of a face voxel are added (chain rule
-    through clamp-to-edge: large terms of both signs). Both relative to the
-    largest reference value among the samples."""
+def assert_close(got, ref, what, bound=None, extra=0.0, floor=FP32_TOL):
+    """Normwise comparison at tol = max(floor, max(bound) / max|ref|) +
+    extra (extra: storage rounding of 16-bit outputs). bound is an array of
+    per-element error bounds shaped like ref (or None: the floor alone)."""
     got = np.asarray(got, dtype=np.float64)
     ref = np.asarray(ref, dtype=np.float64)
-    pos = np.unravel_index(np.asarray(idx), shape)
-    face = np.zeros(len(idx), dtype=bool)
-    for ax in (1, 2, 3):
-        face |= (pos[ax] == 0) | (pos[ax] == shape[ax] - 1)
+    e = normwise(got, ref)
     scale = np.abs(ref).max()
-    err = np.abs(got - ref)
-    e_in = err[~face].max() / scale if (~face).any() else 0.0
-    e_face = err[face].max() / scale if face.any() else 0.0
-    say(f"  {what}: inside {e_in:.3e} (tol {FP32_TOL:.1e}), faces {e_face:.3e} "
-        f"(tol {2 * FP32_TOL:.1e})")
+    b = float(np.max(bound)) / scale if bound is not None and scale > 0 else 0.0
+    tol = max(floor, b) + extra
+    say(f"  {what}: normwise rel err {e:.3e} (bound {b:.2e}, tol {tol:.2e})")
+    say(f"TOL|{what}|{e:.3e}|{b:.3e}|{tol:.3e}")
     assert np.isfinite(got).all(), f"{what}: non-finite output"
-    assert e_in <= FP32_TOL and e_face <= 2 * FP32_TOL, (what, e_in, e_face)
+    assert e <= tol, f"{what}: normwise rel err {e:.3e} > {tol:.2e}"
+
+
+def assert_close_scalar(got, ref, what, bound=None, floor=FP32_TOL):
+    e = abs(got - ref) / abs(ref)
+    b = bound / abs(ref) if bound is not None else 0.0
+    tol = max(floor, b)
+    say(f"  {what}: rel err {e:.3e} (bound {b:.2e}, tol {tol:.2e}); gpu {got!r} oracle {ref!r}")
+    say(f"TOL|{what}|{e:.3e}|{b:.3e}|{tol:.3e}")
+    assert e <= tol, f"{what}: rel err {e:.3e} > {tol:.2e}"
 
 
 def inputs(shape, kind, seed):

@@ -4,11 +4,11 @@ gradient, and the descent driver.
 
 Two errors are reported for 16-bit storage:
   * kernel error: the library against the oracle run on the dequantised
-    inputs (what the kernel itself adds): FP32 outputs within 1e-5,
-    stored volumes within half a storage ulp more;
+    inputs (what the kernel itself adds): FP32 outputs within the FP32
+    tolerance, stored volumes within half a storage ulp more;
   * end-to-end error: against the oracle on the FP32 inputs (what storing the
-    volumes in 16 bits costs); reported, with the stated expectation that it
-    stays within a few storage ulps of max|f| for the volumes.
+    volumes in 16 bits costs); reported, not asserted: it depends on how
+    strongly the weights react to the rounded inputs.
 """
 import numpy as np
 import pytest
@@ -17,8 +17,9 @@ import torch
 import paper_1201_2450_amd as tnlm
 from oracle import oracle
 from phantom import WORKLOADS, quantise, workload_inputs
-from tests.gpu_util import (FP32_TOL, STORE_EPS, assert_close, device, host,
-                            inputs, normwise, say, to_dev, with_peaks)
+from tests.gpu_util import (FP32_TOL, STORE_EPS, U32, Bounds, assert_close,
+                            assert_close_scalar, device, host, inputs, normwise, say,
+                            to_dev, with_peaks)
 from tests.test_gpu_workloads import sample_idx
 
 pytestmark = pytest.mark.gpu
@@ -26,18 +27,37 @@ pytestmark = pytest.mark.gpu
 
 def test_enh32_five_steps_full_volume():
     """Small enhancement workload: weights from the input g for all five
-    Gauss-Jacobi steps, whole-volume comparison after every step."""
+    Gauss-Jacobi steps, whole-volume comparison after every step. Each step
+    is checked against the oracle's step from the GPU's previous iterate (the
+    one-step bound); the five-step result against five oracle steps, where
+    the one-step errors add up at most as sum_k L^k tau_k: with the weights
+    frozen, Eq. (8) is a contraction of modulus L = 2/(2+mu) in the maximum
+    norm (every output is mu/(2+mu) g plus 1/(2+mu) times two convex
+    combinations of f)."""
     w = WORKLOADS["enh32"]
     say(f"enh32 {w.shape}")
     g64, g = to_dev(workload_inputs(w)[0])
+    steps = []
     out = tnlm.enhance(g, w.mu, d=w.d, M=w.M, h=w.h, iters=w.iters,
-                       weights_from="g",
-                       step_hook=None)
+                       weights_from="g", step_hook=lambda k, f: steps.append(f.clone()))
+    torch.cuda.synchronize()
+    assert torch.equal(out, steps[-1])
+    prev = [g] + steps[:-1]
+    taus = []
+    for k in range(w.iters):
+        f64 = host(prev[k])
+        ref = oracle.jacobi(g64, f64, g64, w.mu, w.d, w.M, w.h)
+        b = Bounds(g64, f64, w.d, w.M, w.h).jacobi(w.mu)
+        assert_close(host(steps[k]), ref, f"enh32 step {k}", b)
+        taus.append(max(FP32_TOL * np.abs(ref).max(), float(b.max())))
     f = g64.copy()
     for _ in range(w.iters):
         f = oracle.jacobi(g64, f, g64, w.mu, w.d, w.M, w.h)
-    torch.cuda.synchronize()
-    assert_close(host(out), f, w.iters * FP32_TOL, "f after 5 steps")
+    L = 2.0 / (2.0 + w.mu)
+    acc = sum(L ** (w.iters - 1 - k) * t for k, t in enumerate(taus))
+    err = np.abs(host(out) - f).max()
+    say(f"  five steps: max abs err {err:.3e}, accumulated bound {acc:.3e}")
+    assert err <= acc
     # the full weight tensor of this workload (164 MB) at sampled voxels
     wt, lse = tnlm.weights(g, d=w.d, M=w.M, h=w.h, want_w=True)
     torch.cuda.synchronize()
@@ -45,8 +65,9 @@ def test_enh32_five_steps_full_volume():
     idx = sample_idx(w.shape, 200, 8)
     wr, lr = oracle.weights(g64, w.d, w.M, w.h)
     i, v = idx // N, idx % N
-    assert_close(host(wt)[i, :, :, v], wr[i, :, :, v], FP32_TOL, "w (sampled)")
-    assert_close(host(lse), lr, FP32_TOL, "lse")
+    B = Bounds(g64, g64, w.d, w.M, w.h)
+    assert_close(host(wt)[i, :, :, v], wr[i, :, :, v], "w (sampled)", B.w()[i, :, :, v])
+    assert_close(host(lse), lr, "lse", B.lse())
 
 
 @pytest.mark.parametrize("storage", ["bf16", "f16"])
@@ -85,13 +106,18 @@ def test_storage_error_tables(storage):
         rows.append((name, errs))
         say(f"  {storage} {name:10s} " + "  ".join(f"{k} {v:.2e}"
                                                   for k, v in errs.items()))
+    # kernel error: the derived bounds of the dequantised case; the sampled
+    # gradient takes the floor (its bound needs the whole-grid scatter model)
+    B = Bounds(xq64, xq64, d, M, h, idx=idx)
+    tol = lambda bnd, ref: max(FP32_TOL, float(np.max(bnd)) / np.abs(ref).max())
+    kref = oracle.jacobi(xq64, xq64, xq64, mu, d, M, h, idx=idx)
     kern = rows[0][1]
-    assert kern["jacobi"] <= FP32_TOL + STORE_EPS[storage]
-    for k in ("lse", "grad", "energy"):
-        assert kern[k] <= FP32_TOL, (k, kern[k])
-    # storing the volumes in 16 bits: a few storage ulps on the volumes
-    e2e = rows[1][1]
-    assert e2e["jacobi"] <= 8 * STORE_EPS[storage]
+    assert kern["jacobi"] <= tol(B.jacobi(mu), kref) + STORE_EPS[storage]
+    lref = oracle.stats(xq64, xq64, d, M, h, idx=idx)[:, :, 0]
+    assert kern["lse"] <= tol(B.lse(), lref), kern["lse"]
+    assert kern["grad"] <= FP32_TOL, kern["grad"]
+    Bw = Bounds(xq64, xq64, d, M, h)
+    assert kern["energy"] <= max(FP32_TOL, Bw.energy() / abs(oracle.energy(xq64, xq64, d, M, h)))
 
 
 def test_fbs512_fp16_gradient_sampled():
@@ -108,7 +134,8 @@ def test_fbs512_fp16_gradient_sampled():
     f64 = f16.astype(np.float64)
     rf, ru = oracle.grad_exact_at(f64, f64, w.d, w.M, w.h, idx)
     g32 = gt.cpu().numpy().ravel()[idx]
-    assert_close(g32, rf + ru, FP32_TOL, "dE/df total (sampled)")
+    # floor only: the gradient's bound needs the whole-grid scatter model
+    assert_close(g32, rf + ru, "dE/df total (sampled)", None)
     step = tnlm.descend(f, d=w.d, M=w.M, h=w.h, tau=0.1, iters=1)
     torch.cuda.synchronize()
     # the update is float32 arithmetic rounded to FP16, as in the driver
@@ -119,16 +146,26 @@ def test_fbs512_fp16_gradient_sampled():
 
 
 def test_descent_driver_matches_oracle_steps():
+    """Three descent steps f <- f - tau dE(f; f)/df. The driver's result is
+    bitwise three one-step calls; each step matches the oracle's step from
+    the GPU's previous iterate within tau times the gradient's bound plus the
+    FP32 rounding of the update (u (|f| + tau |grad|) per voxel)."""
     shape, d, M, h, tau = (3, 8, 9, 10), 1, 2, 0.08, 0.05
     say(f"descent {shape}")
     f64, f = to_dev(inputs(shape, "phantom", 32))
     out = tnlm.descend(f, d=d, M=M, h=h, tau=tau, iters=3)
-    x = f64.copy()
-    for _ in range(3):
-        a, b = oracle.grad_exact_scatter(x, x, d, M, h)
-        x = quantise(x - tau * (a + b), "f32")[0]
-    torch.cuda.synchronize()
-    assert_close(host(out), x, 3 * FP32_TOL, "f after 3 descent steps")
+    x = f
+    for k in range(3):
+        x64 = host(x)
+        nxt = tnlm.descend(x, d=d, M=M, h=h, tau=tau, iters=1)
+        torch.cuda.synchronize()
+        a, b = oracle.grad_exact_scatter(x64, x64, d, M, h)
+        ref = x64 - tau * (a + b)
+        bound = tau * Bounds(x64, x64, d, M, h, grad=True).total() + \
+            U32 * (np.abs(x64) + tau * np.abs(a + b))
+        assert_close(host(nxt), ref, f"descent step {k}", bound)
+        x = nxt
+    assert torch.equal(out, x)
 
 
 def test_enhancement_removes_streaks_and_raises_lesion_cnr():

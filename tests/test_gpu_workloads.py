@@ -13,8 +13,8 @@ import torch
 import paper_1201_2450_amd as tnlm
 from oracle import oracle
 from phantom import WORKLOADS, quantise, workload_inputs
-from tests.gpu_util import (FP32_TOL, assert_close, device, host, inputs, say, to_dev,
-                            with_peaks)
+from tests.gpu_util import (FP32_TOL, Bounds, assert_close, assert_close_scalar, device,
+                            host, inputs, say, to_dev, with_peaks)
 
 pytestmark = pytest.mark.gpu
 
@@ -48,15 +48,15 @@ def test_interior_tiles_forward_modes():
     _, lse = tnlm.weights(u, d=d, M=M, h=h)
     e, st = tnlm.energy(f, u=u, d=d, M=M, h=h, want_stats=True)
     torch.cuda.synchronize()
-    assert_close(host(out), oracle.jacobi(u64, f64, g64, mu, d, M, h),
-                 FP32_TOL, "jacobi")
-    assert_close(host(g6), oracle.grad_eq6(u64, f64, d, M, h), FP32_TOL,
-                 "eq6")
+    B = Bounds(u64, f64, d, M, h)
+    assert_close(host(out), oracle.jacobi(u64, f64, g64, mu, d, M, h), "jacobi",
+                 B.jacobi(mu))
+    assert_close(host(g6), oracle.grad_eq6(u64, f64, d, M, h), "eq6", B.eq6())
     E_ref, st_ref = oracle.energy(u64, f64, d, M, h, want_stats=True)
-    assert_close(host(lse), st_ref[:, :, 0], FP32_TOL, "lse")
-    assert_close(host(st), st_ref, FP32_TOL, "stats")
+    assert_close(host(lse), st_ref[:, :, 0], "lse", B.lse())
+    assert_close(host(st), st_ref, "stats", B.stats())
     E = float(e[0]) + float(e[1])
-    assert abs(E - E_ref) <= FP32_TOL * abs(E_ref), (E, E_ref)
+    assert_close_scalar(E, E_ref, "E", B.energy())
 
 
 def test_interior_tiles_largest_tiled_window_sampled():
@@ -73,13 +73,14 @@ def test_interior_tiles_largest_tiled_window_sampled():
     _, lse = tnlm.weights(u, d=d, M=M, h=h)
     torch.cuda.synchronize()
     idx = with_peaks(sample_idx(shape, 300, 7), out, g6)
+    B = Bounds(u64, f64, d, M, h, idx=idx)
     assert_close(host(out).ravel()[idx],
-                 oracle.jacobi(u64, f64, g64, mu, d, M, h, idx=idx), FP32_TOL, "jacobi")
+                 oracle.jacobi(u64, f64, g64, mu, d, M, h, idx=idx), "jacobi", B.jacobi(mu))
     assert_close(host(g6).ravel()[idx],
-                 oracle.grad_eq6(u64, f64, d, M, h, idx=idx), FP32_TOL, "eq6")
+                 oracle.grad_eq6(u64, f64, d, M, h, idx=idx), "eq6", B.eq6())
     N = int(np.prod(shape[1:]))
     st = oracle.stats(u64, u64, d, M, h, idx=idx)
-    assert_close(host(lse)[idx // N, :, idx % N], st[:, :, 0], FP32_TOL, "lse")
+    assert_close(host(lse)[idx // N, :, idx % N], st[:, :, 0], "lse", B.lse())
 
 
 def test_interior_tiles_exact_gradient_sampled():
@@ -91,8 +92,9 @@ def test_interior_tiles_exact_gradient_sampled():
     torch.cuda.synchronize()
     idx = with_peaks(sample_idx(shape, 160, 3), gf, gu)
     rf, ru = oracle.grad_exact_at(u64, f64, d, M, h, idx)
-    assert_close(host(gf).ravel()[idx], rf, FP32_TOL, "dE/df (sampled)")
-    assert_close(host(gu).ravel()[idx], ru, FP32_TOL, "dE/du (sampled)")
+    B = Bounds(u64, f64, d, M, h, grad=True)
+    assert_close(host(gf).ravel()[idx], rf, "dE/df (sampled)", B.gf().ravel()[idx])
+    assert_close(host(gu).ravel()[idx], ru, "dE/du (sampled)", B.gu().ravel()[idx])
 
 
 def test_enh256_jacobi_step_sampled():
@@ -107,14 +109,15 @@ def test_enh256_jacobi_step_sampled():
     idx = with_peaks(sample_idx(w.shape, 400, 4), out)
     g64 = g32.astype(np.float64)
     ref = oracle.jacobi(g64, g64, g64, w.mu, w.d, w.M, w.h, idx=idx)
-    assert_close(host(out).ravel()[idx], ref, FP32_TOL, "f_out (sampled)")
+    B = Bounds(g64, g64, w.d, w.M, w.h, idx=idx)
+    assert_close(host(out).ravel()[idx], ref, "f_out (sampled)", B.jacobi(w.mu))
     # log-normalisers at the same voxels
     _, lse = tnlm.weights(g, d=w.d, M=w.M, h=w.h)
     st = oracle.stats(g64, g64, w.d, w.M, w.h, idx=idx)
     N = w.nx * w.ny * w.nz
     i, v = idx // N, idx % N
     got = host(lse)[i, :, v]
-    assert_close(got, st[:, :, 0], FP32_TOL, "lse (sampled)")
+    assert_close(got, st[:, :, 0], "lse (sampled)", B.lse())
 
 
 @pytest.mark.parametrize("storage", ["bf16", "f16"])
@@ -127,7 +130,8 @@ def test_enh256_storage_jacobi_sampled(storage):
     idx = with_peaks(sample_idx(w.shape, 200, 5), out)
     ref = oracle.jacobi(g64q, g64q, g64q, w.mu, w.d, w.M, w.h, idx=idx)
     eps = 2.0 ** -8 if storage == "bf16" else 2.0 ** -11
-    assert_close(host(out).ravel()[idx], ref, FP32_TOL + eps, "f_out")
+    B = Bounds(g64q, g64q, w.d, w.M, w.h, idx=idx)
+    assert_close(host(out).ravel()[idx], ref, "f_out", B.jacobi(w.mu), extra=eps)
 
 
 def test_energy128_energy_and_adjoint_sampled():
@@ -150,12 +154,17 @@ def test_energy128_energy_and_adjoint_sampled():
     idx = with_peaks(sample_idx(w.shape, 64, 6), gt)
     N = w.nx * w.ny * w.nz
     ref_st = oracle.stats(f64, f64, w.d, w.M, w.h, idx=idx)
-    assert_close(sth[idx // N, :, :, idx % N], ref_st, FP32_TOL, "stats")
+    B = Bounds(f64, f64, w.d, w.M, w.h, idx=idx)
+    assert_close(sth[idx // N, :, :, idx % N], ref_st, "stats", B.stats())
     gidx = with_peaks(idx[::2], gt)
     rf, ru = oracle.grad_exact_at(f64, f64, w.d, w.M, w.h, gidx)
-    assert_close(host(gt).ravel()[gidx], rf + ru, FP32_TOL, "dE/df total")
-    # central differences of the FP64 local energy (eps = 1e-3, with a
-    # Richardson step at eps/2 to remove the O(eps^2) truncation)
+    # the gradient's bound needs the whole-grid scatter model, too slow at
+    # this size: the floor alone applies (no looser than the derived bound)
+    assert_close(host(gt).ravel()[gidx], rf + ru, "dE/df total", None)
+    # central differences of the FP64 local energy, Richardson-extrapolated
+    # from steps eps and eps/2 (removing the O(eps^2) term); the remaining
+    # truncation is O(eps^4), so the extrapolate from eps/2 and eps/4 is
+    # 16x closer and the difference of the two estimates its error
     ghost = host(gt).ravel()
     scale = np.abs(rf + ru).max()
 
@@ -168,8 +177,9 @@ def test_energy128_energy_and_adjoint_sampled():
 
     for flat in gidx[:12]:
         pos = tuple(int(c) for c in np.unravel_index(int(flat), w.shape))
-        d1, d2 = cd(pos, 1e-3), cd(pos, 5e-4)
-        fd = (4 * d2 - d1) / 3
-        say(f"  FD at {pos}: gpu {ghost[flat]:.6e} fd(1e-3) {d1:.6e} "
-            f"richardson {fd:.6e}")
-        assert abs(ghost[flat] - fd) <= 1e-4 * scale
+        d1, d2, d4 = cd(pos, 1e-3), cd(pos, 5e-4), cd(pos, 2.5e-4)
+        r1, r2 = (4 * d2 - d1) / 3, (4 * d4 - d2) / 3
+        trunc = abs(r1 - r2) / 15
+        say(f"  FD at {pos}: gpu {ghost[flat]:.6e} richardson {r2:.6e} "
+            f"(truncation ~{trunc:.1e})")
+        assert abs(ghost[flat] - r2) <= FP32_TOL * scale + trunc

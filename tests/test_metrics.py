@@ -39,3 +39,28 @@ def test_srr_limits():
     half = 0.5 * (t + fin)
     ref = np.mean([metrics_ref.srr(fin[i], half[i], t[i]) for i in range(2)])
     assert abs(metrics.srr(ti, torch.from_numpy(half), tt) - ref) <= 1e-12
+
+
+def test_cnr_closed_form_two_level_regions():
+    """Regions whose mean and population standard deviation are exact by
+    construction: a two-level pattern c +- s with as many + as - voxels has
+    mean c and standard deviation s, so CNR = 2|c_roi - c_bg| / (s_roi + s_bg)
+    (Sec. 2.5) without evaluating any moment numerically."""
+    vol = np.zeros((6, 6, 6))
+    roi = np.zeros(vol.shape, bool)
+    bg = np.zeros(vol.shape, bool)
+    roi[:2] = True          # 72 voxels
+    bg[3:] = True           # 108 voxels
+    sign = np.where((np.indices(vol.shape).sum(axis=0) % 2) == 0, 1.0, -1.0)
+    c_roi, s_roi, c_bg, s_bg = 0.25, 0.0625, 0.125, 0.03125
+    vol[roi] = c_roi + s_roi * sign[roi]
+    vol[bg] = c_bg + s_bg * sign[bg]
+    assert sign[roi].sum() == 0 and sign[bg].sum() == 0
+    want = 2 * abs(c_roi - c_bg) / (s_roi + s_bg)   # = 8/3
+    assert abs(metrics_ref.cnr(vol, roi, bg) - want) <= 1e-14
+    got = metrics.cnr(torch.from_numpy(vol), torch.from_numpy(roi), torch.from_numpy(bg))
+    assert abs(got - want) <= 1e-14
+    # the sample (n-1) standard deviation would give a different value
+    n = roi.sum()
+    assert abs(2 * abs(c_roi - c_bg) / (s_roi * np.sqrt(n / (n - 1))
+                                        + s_bg * np.sqrt(bg.sum() / (bg.sum() - 1))) - want) > 1e-3
