@@ -39,6 +39,7 @@ PEAK_FP32_NONPACKED_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 
 # squared difference 2 + separable 3-tap box sums 6 (once per link), then per
 # direction: exponent 2, numerator FMA 2, normaliser add 1 (x2 directions)
 FLOP_PER_UPDATE_PER_OFFSET = 18
+FLOP_PER_VOXEL_OFFSET_ADJOINT = 35
 
 
 def log(*a):
@@ -69,6 +70,18 @@ def profile_figures():
         return {}
 
 
+def cpu_model():
+    """The host CPU's model name (first 'model name' of /proc/cpuinfo)."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.lower().startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(w, target_s):
     """Time the FP64 oracle on a bounded sample of the same workload: one
     Jacobi step (u = f = g) at a random sample of voxels."""
@@ -93,10 +106,35 @@ def cpu_baseline(w, target_s):
     n2, dt = n_all, t_all
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": n2 / dt, "unit": "voxel-updates/s", "cores": threads,
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": cpu_model(),
             "sample": f"one Gauss-Jacobi step of the 10x256x256x128 "
                       f"workload (u=f=g) at {n2} random voxels, FP64, "
                       f"{dt:.1f} s on {threads} OpenMP threads"}
+
+
+def cpu_baseline_gradient(f64, w, target_s):
+    """The FP64 oracle's exact gradient of E(f; f) (gather form, the part
+    that dominates the regulariser step) at random voxels of the same
+    volume, in batches until target_s of oracle time has been spent."""
+    import numpy as np
+
+    from oracle import oracle
+    rng = np.random.default_rng(8)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    n_all, t_all, n = 0, 0.0, threads
+    while t_all < target_s:
+        idx = rng.choice(f64.size, size=n, replace=False)
+        t0 = time.perf_counter()
+        oracle.grad_exact_at(f64, f64, w.d, w.M, w.h, idx)
+        t_all += time.perf_counter() - t0
+        n_all += n
+        rate = n_all / t_all
+        n = int(max(threads, rate * min(max(target_s - t_all, 0.0), 5.0)))
+    return {"value": n_all / t_all, "unit": "voxel-updates/s", "cores": threads,
+            "kind": "oracle", "cpu_model": cpu_model(),
+            "sample": f"exact gradient of E(f; f) of the {w.name} volume "
+                      f"(FP16 values) at {n_all} random voxels, FP64 gather form, "
+                      f"{t_all:.1f} s on {threads} OpenMP threads"}
 
 
 def regulariser(args, w, dev):
@@ -145,6 +183,24 @@ def regulariser(args, w, dev):
     ms_step = 1e3 * (time.perf_counter() - t0) / args.steps
     ms = {n: float(np.mean([e[n][0].elapsed_time(e[n][1]) for e in evs])) for n in names}
     log(f"step {ms_step:.1f} ms; per-op ms {ms}")
+    # dominant kernel: the exact adjoint. Algorithmic flop per voxel and
+    # offset, patch 3^3: distance 8 (once per link), two weights 2 x 2,
+    # centred terms 8, box sum back 6, times Delta 3, image part 3 = 32,
+    # rounded up to 35 (plus two exponentials)
+    W = (2 * M + 1) ** 3
+    alg = FLOP_PER_VOXEL_OFFSET_ADJOINT * W * w.nvox
+    ach = alg / (ms["adjoint"] / 1e3) / 1e12
+    roofline = {"bound": "alu", "achieved": ach, "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s", "frac": ach / PEAK_FP32_TFLOPS, "traffic": None,
+                "kernel": "tnlm_grad (exact adjoint)",
+                "algorithmic_flop_per_launch": alg,
+                "peak_without_packed_fp32": PEAK_FP32_NONPACKED_TFLOPS,
+                "frac_without_packed_fp32": ach / PEAK_FP32_NONPACKED_TFLOPS}
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the FP64 oracle gradient on a sample ...")
+        cpu = cpu_baseline_gradient(f.float().cpu().numpy().astype(np.float64), w,
+                                    args.cpu_seconds)
     print(json.dumps({
         "metric": METRIC, "value": w.nvox / (ms_step / 1e3), "unit": "voxel-updates/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -154,7 +210,7 @@ def regulariser(args, w, dev):
         "config": {"workload": w.name, "phases": w.np_, "grid": [w.nx, w.ny, w.nz],
                    "patch": 2 * d + 1, "window": 2 * M + 1, "h": h, "tau": tau,
                    "step": "energy + exact adjoint + descent update"},
-        "breakdown_ms": ms, "roofline": None, "cpu_baseline": None}), flush=True)
+        "breakdown_ms": ms, "roofline": roofline, "cpu_baseline": cpu}), flush=True)
 
 
 def main():
@@ -285,11 +341,28 @@ def main():
         return e0.elapsed_time(e1) / reps
 
     # storage formats compared on one call pattern: a Jacobi step with
-    # u = f = g (the noisy input) and energy + adjoint of g, in each format
+    # u = f = g (the noisy input) and energy + adjoint of g, in each format;
+    # then the whole mixed-precision workload (20 steps, weights every 5,
+    # log-normalisers, energy, exact gradient) in each format, timed, and its
+    # outputs compared with the FP32 run's at every voxel
+    def rel(a, b):
+        dd = a.double() - b.double()
+        return {"max": float(dd.abs().max() / b.double().abs().max()),
+                "rms": float(dd.square().mean().sqrt() / b.double().square().mean().sqrt())}
+
+    def c4_run(gq):
+        fq = tnlm.enhance(gq, mu, d=d, M=M, h=h, iters=iters, recompute_every=every)
+        _, lq = tnlm.weights(fq, d=d, M=M, h=h)
+        eq, sq = tnlm.energy(fq, d=d, M=M, h=h, want_stats=True)
+        gtq = tnlm.grad(fq, d=d, M=M, h=h, mode="exact", stats=sq, total=True)
+        return fq, lq, eq, gtq
+
     dtypes = {}
+    ref = {}
     if not args.no_dtypes:
         for name, dt in (("f32", torch.float32), ("bf16", torch.bfloat16),
                          ("f16", torch.float16)):
+            log(f"storage format {name} ...")
             gq = g.to(dt)
             outq = torch.empty_like(gq)
             tnlm.jacobi_step(gq, gq, gq, mu, d=d, M=M, h=h, out=outq)
@@ -304,14 +377,41 @@ def main():
             jms = e0.elapsed_time(e1) / reps
 
             def energy_adjoint():
-                _, st = tnlm.energy(gq, d=d, M=M, h=h, want_stats=True)
-                return tnlm.grad(gq, d=d, M=M, h=h, mode="exact", stats=st, total=True)
+                ee, st = tnlm.energy(gq, d=d, M=M, h=h, want_stats=True)
+                return ee, tnlm.grad(gq, d=d, M=M, h=h, mode="exact", stats=st, total=True)
 
             eams = time_ms(energy_adjoint)
-            dtypes[name] = {"jacobi_ms": jms,
-                            "jacobi_voxel_updates_per_s": nvox / (jms / 1e3),
-                            "energy_plus_adjoint_ms": eams}
-            del gq, outq
+            e1q, gr1 = energy_adjoint()
+            c4_run(gq)
+            torch.cuda.synchronize()
+            e0, e1 = EV(), EV()
+            e0.record()
+            fq, lq, eq, gtq = c4_run(gq)
+            e1.record()
+            torch.cuda.synchronize()
+            res = {"jacobi_ms": jms,
+                   "jacobi_voxel_updates_per_s": nvox / (jms / 1e3),
+                   "energy_plus_adjoint_ms": eams,
+                   "workload_ms": e0.elapsed_time(e1),
+                   "workload": "20 Jacobi (weights every 5) + lse + energy + exact gradient"}
+            one = {"jacobi": outq, "E": float(e1q[0]) + float(e1q[1]), "grad": gr1}
+            run = {"f20": fq, "lse": lq, "E": float(eq[0]) + float(eq[1]), "grad20": gtq}
+            if name == "f32":
+                ref = {"one": one, "run": run}
+            else:
+                # errors against the FP32 form: largest and rms, relative
+                res["err_jacobi_one_step_vs_f32"] = rel(one["jacobi"], ref["one"]["jacobi"])
+                res["err_energy_vs_f32"] = abs(one["E"] - ref["one"]["E"]) / abs(ref["one"]["E"])
+                res["err_grad_vs_f32"] = rel(one["grad"], ref["one"]["grad"])
+                res["err_workload_f20_vs_f32"] = rel(run["f20"], ref["run"]["f20"])
+                res["err_workload_lse_vs_f32"] = rel(run["lse"], ref["run"]["lse"])
+                res["err_workload_energy_vs_f32"] = \
+                    abs(run["E"] - ref["run"]["E"]) / abs(ref["run"]["E"])
+                res["err_workload_grad_vs_f32"] = rel(run["grad20"], ref["run"]["grad20"])
+            dtypes[name] = res
+            del gq, outq, one, run, fq, lq, gtq, gr1
+        del ref
+        torch.cuda.empty_cache()
 
     # the differentiable form against the plain calls it wraps: energy with
     # statistics + exact adjoint, vs autograd forward + backward of E(f; f)
