@@ -471,6 +471,411 @@ __global__ void __launch_bounds__(256) fold_kernel(Geo g, const float *gpad, flo
     }
 }
 
+// ---------------------------------------------------------------------------
+// Two-stage adjoint for u = f (the gradient of E(f; f)), M <= 4.
+//
+// The per-lane blocks above evaluate the distance and Gv on positions grown
+// by a halo around each lane's outputs (4 x 6 Gv positions for 2 x 4
+// outputs, two exponentials each). Here a workgroup evaluates Gv once per
+// position of its tile (stage 1) into an LDS field, and box-sums that field
+// back onto its outputs (stage 2), so every exponential serves the 27
+// outputs around its position:
+//   * tile: TX (x) x 28 (y) x TZ (z) padded outputs of one phase, 16
+//     32-lane segments (512 threads); lane l of every segment sits on grid
+//     row Y0 - 3 + l;
+//   * stage 1: segment s takes a 3 (x) x 4 (z) block of the 6 x 32 Gv
+//     positions (grid x X0-2 .. X0+3, z Z0-2 .. Z0+29): squared differences
+//     on its 5 x 6 block, box sums along z, x (pair sums shared) and y (DPP),
+//     both weights, Gv and the image part; Gv goes to LDS;
+//   * stage 2: segment s < 15 owns 4 (x) x 2 (z) outputs: reads the 6 x 4
+//     Gv block around them, box sums along z, x and y (DPP), multiplies by
+//     Delta = U_k(q') - U_j(q' + delta) and accumulates;
+//   * u_j and the neighbour's statistics are staged per dx as above; per
+//     (dy, dz) pair one barrier sits between stage 1's arithmetic and its
+//     Gv stores (so the previous pair's stage-2 reads are done) and one
+//     between the stores and stage 2.
+// ---------------------------------------------------------------------------
+namespace v2 {
+constexpr int TX = 4, TY = 28, TZ = 14;  // padded outputs per tile
+constexpr int GX = TX + 2, GZ = TZ + 2;  // Gv positions (x, z)
+constexpr int SX = TX + 4, SZ = TZ + 4;  // squared-difference positions
+constexpr int B1X = 3, B1Z = 4;          // stage-1 block (Gv positions)
+constexpr int B2X = TX, B2Z = 2;         // stage-2 block (outputs)
+constexpr int NSEG = 8, THREADS = 32 * NSEG;
+constexpr int NSEG2 = TZ / B2Z;  // segments with stage-2 outputs (15)
+static_assert(GX == 2 * B1X && GZ == (NSEG / 2) * B1Z, "stage-1 blocks tile the Gv field");
+static_assert(NSEG2 <= NSEG && TZ % B2Z == 0, "stage-2 blocks tile the outputs");
+constexpr int kMaxM = 4;
+
+template <int M>
+struct Lay {
+    static constexpr int UR = 32 + 2 * M;  // u_j rows (lanes 0..31, +-M)
+    static constexpr int UZ = SZ + 2 * M;  // u_j z
+    static constexpr int RU = (SX * UZ) | 1;
+    static constexpr int SR = 32 + 2 * M;  // statistics rows
+    static constexpr int SZL = GZ + 2 * M; // statistics z
+    static constexpr int RS = (2 * GX * SZL) | 1;
+    static constexpr int RG = (GX * GZ) | 1;  // Gv field row stride
+    // Gv rows of lanes 1..30, plus one row that lanes 0 and 31 (incomplete
+    // distances, unused outputs) write to; they read rows of lanes 1 and 30
+    static constexpr int NU = UR * RU, NS = SR * RS, NG = 31 * RG;
+    static_assert((B1X + 1) * UZ + B1Z + 2 < 256, "stage-1 u_j reads reach by ds_read2 offsets");
+    static_assert(2 * ((B1X - 1) * SZL + B1Z) < 256, "statistics reads reach");
+    static_assert((GX - 1) * GZ + 4 < 256, "stage-2 Gv reads reach");
+    static_assert((NU + NS + NG) * 4 <= 160 * 1024, "fits the LDS of one CU");
+    // up to M = 3 two workgroups share a CU (one computes while the other
+    // waits at a barrier)
+    static_assert(M > 3 || (NU + NS + NG) * 4 <= 80 * 1024, "two workgroups per CU");
+};
+
+struct Grid {
+    int ntx, nty, ntz, nblocks;
+};
+
+template <typename T, int M>
+__global__ void __launch_bounds__(THREADS) grad_lds_kernel(Geo g, GradArgs a, float *gpad, Grid gg)
+{
+    using L = Lay<M>;
+    __shared__ float lds[L::NU + L::NS + L::NG];
+    float *sU = lds, *sS = lds + L::NU, *sG = lds + L::NU + L::NS;
+
+    const int b = blockIdx.x;
+    const int q8 = gg.nblocks >> 3, r8 = gg.nblocks & 7, xcd = b & 7;
+    int t = xcd * q8 + min(xcd, r8) + (b >> 3);
+    const int tz = t % gg.ntz;
+    t /= gg.ntz;
+    const int ty = t % gg.nty;
+    t /= gg.nty;
+    const int tx = t % gg.ntx;
+    const int k = t / gg.ntx;
+    const int X0 = tx * TX, Y0 = ty * TY, Z0 = tz * TZ;  // padded tile origin
+
+    const int tid = threadIdx.x;
+    const int seg = tid >> 5;  // 32-lane segment (two per wave)
+    const int l = tid & 31;
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    const int64_t N = g.N;
+    const T *u = (const T *)a.u;
+    const int y = Y0 - 3 + l;  // grid row of this lane
+    const int yc = clampi(y, 0, ny - 1);
+    auto vox = [&](int ph, int xx, int yy, int zz) -> int64_t {
+        return (int64_t)ph * N + ((int64_t)xx * ny + yy) * nz + zz;
+    };
+    auto st = [&](int ph, int slot, int comp, int xx, int yy, int zz) -> float {
+        return a.stats[(((int64_t)ph * 2 + slot) * 2 + comp) * N + ((int64_t)xx * ny + yy) * nz + zz];
+    };
+
+    // stage-1 block: Gv x [ex0, ex0+3), z [ez0, ez0+4); squared differences
+    // on x [ex0, ex0+5) (sq index s <-> grid X0-3+s), z [ez0, ez0+6)
+    const int ex0 = B1X * (seg / (NSEG / 2)), ez0 = B1Z * (seg % (NSEG / 2));
+    float uk[B1X + 2][B1Z + 2];
+#pragma unroll
+    for (int s = 0; s < B1X + 2; ++s)
+#pragma unroll
+        for (int c = 0; c < B1Z + 2; ++c)
+            uk[s][c] = load_f(u, vox(k, clampi(X0 - 3 + ex0 + s, 0, nx - 1), yc,
+                                     clampi(Z0 - 3 + ez0 + c, 0, nz - 1)));
+    // stage-2 block: outputs padded x X0 .. X0+3, z Z0+2 seg .. +1 (grid = padded - 1)
+    const bool has2 = seg < NSEG2;
+    const int oz0 = B2Z * (has2 ? seg : 0);
+    float uk2[B2X][B2Z], gw[B2X][B2Z];
+#pragma unroll
+    for (int xo = 0; xo < B2X; ++xo)
+#pragma unroll
+        for (int zo = 0; zo < B2Z; ++zo) {
+            uk2[xo][zo] = load_f(u, vox(k, clampi(X0 + xo - 1, 0, nx - 1), yc,
+                                        clampi(Z0 + oz0 + zo - 1, 0, nz - 1)));
+            gw[xo][zo] = 0.f;
+        }
+    float gi[B1X][B1Z];
+#pragma unroll
+    for (int ex = 0; ex < B1X; ++ex)
+#pragma unroll
+        for (int ez = 0; ez < B1Z; ++ez)
+            gi[ex][ez] = 0.f;
+
+    // masks are needed when some Gv position of the tile (rows of lanes
+    // 0..31 included) has v or v + delta outside the grid
+    const bool border = (X0 - 2 - M < 0) || (X0 + TX - 1 + M >= nx) || (Y0 - 3 - M < 0) ||
+                        (Y0 + 28 + M >= ny) || (Z0 - 2 - M < 0) || (Z0 + TZ - 1 + M >= nz);
+    const float c2 = g.c2;
+    constexpr int S = 2 * M + 1;
+    const bool want_u = gpad != nullptr;  // uniform: without dE/du only stage 1 runs
+
+    for (int slot = 0; slot < 2; ++slot) {
+        const int j = slot == 0 ? (k + 1 == g.np ? 0 : k + 1) : (k == 0 ? g.np - 1 : k - 1);
+        const int back = 1 - slot;
+        float L1[B1X][B1Z], e1[B1X][B1Z];
+#pragma unroll
+        for (int ex = 0; ex < B1X; ++ex)
+#pragma unroll
+            for (int ez = 0; ez < B1Z; ++ez) {
+                const int xx = clampi(X0 - 2 + ex0 + ex, 0, nx - 1);
+                const int zz = clampi(Z0 - 2 + ez0 + ez, 0, nz - 1);
+                L1[ex][ez] = -st(k, slot, 0, xx, yc, zz) * kLog2e;
+                e1[ex][ez] = st(k, slot, 1, xx, yc, zz);
+            }
+        auto sweep = [&](auto bord_c) {
+            constexpr bool bord = decltype(bord_c)::value;
+            for (int dx = -M; dx <= M; ++dx) {
+                __syncthreads();
+                {
+                    const int64_t plane = (int64_t)ny * nz;
+                    const T *up[SX];
+                    const float *lp[GX];
+#pragma unroll
+                    for (int p = 0; p < SX; ++p)
+                        up[p] = u + (int64_t)j * N + clampi(X0 - 3 + dx + p, 0, nx - 1) * plane;
+#pragma unroll
+                    for (int p = 0; p < GX; ++p)
+                        lp[p] = a.stats + ((int64_t)j * 2 + back) * 2 * N +
+                                clampi(X0 - 2 + dx + p, 0, nx - 1) * plane;
+                    for (int c = tid; c < L::UR * L::UZ; c += THREADS) {
+                        const int r = c / L::UZ, zc = c - r * L::UZ;
+                        const int gy = clampi(Y0 - 3 - M + r, 0, ny - 1);
+                        const int gz = clampi(Z0 - 3 - M + zc, 0, nz - 1);
+                        const unsigned co = (unsigned)(gy * nz + gz) * (unsigned)sizeof(T);
+                        float *su = sU + r * L::RU + zc;
+#pragma unroll
+                        for (int p = 0; p < SX; ++p)
+                            su[p * L::UZ] = load_f((const T *)((const char *)up[p] + co), 0);
+                    }
+                    for (int c = tid; c < L::SR * L::SZL; c += THREADS) {
+                        const int r = c / L::SZL, zc = c - r * L::SZL;
+                        const int gy = clampi(Y0 - 3 - M + r, 0, ny - 1);
+                        const int gz = clampi(Z0 - 2 - M + zc, 0, nz - 1);
+                        const unsigned co = (unsigned)(gy * nz + gz);
+                        float *ss = sS + r * L::RS + 2 * zc;
+#pragma unroll
+                        for (int p = 0; p < GX; ++p) {
+                            ss[2 * p * L::SZL] = -lp[p][co] * kLog2e;
+                            ss[2 * p * L::SZL + 1] = lp[p][co + N];
+                        }
+                    }
+                }
+                __syncthreads();
+                for (int pr = 0; pr < S * S; ++pr) {
+                    const int dy = pr / S - M, dz = pr - (pr / S) * S - M;
+                    // ---- stage 1: D and Gv on this segment's block
+                    {
+                        lds_float *bu = lds_base(sU + (l + M + dy) * L::RU + ex0 * L::UZ + ez0 + M + dz);
+                        lds_float *bs = lds_base(sS + (l + M + dy) * L::RS + 2 * (ex0 * L::SZL + ez0 + M + dz));
+                        float ub[B1X + 2][B1Z + 2];
+#pragma unroll
+                        for (int s = 0; s < B1X + 2; ++s)
+#pragma unroll
+                            for (int c = 0; c < B1Z + 2; ++c)
+                                ub[s][c] = bu[s * L::UZ + c];
+                        float sl[B1X][B1Z], se[B1X][B1Z];
+#pragma unroll
+                        for (int ex = 0; ex < B1X; ++ex)
+#pragma unroll
+                            for (int ez = 0; ez < B1Z; ++ez) {
+                                sl[ex][ez] = bs[2 * (ex * L::SZL + ez)];
+                                se[ex][ez] = bs[2 * (ex * L::SZL + ez) + 1];
+                            }
+                        __builtin_amdgcn_sched_barrier(0);
+                        float pz[B1X + 2][B1Z], rc[B1X][B1Z];
+#pragma unroll
+                        for (int s = 0; s < B1X + 2; ++s) {
+                            float dd[B1Z + 2];
+#pragma unroll
+                            for (int c = 0; c < B1Z + 2; ++c)
+                                dd[c] = uk[s][c] - ub[s][c];
+                            if (s >= 1 && s <= B1X) {
+#pragma unroll
+                                for (int ez = 0; ez < B1Z; ++ez)
+                                    rc[s - 1][ez] = dd[ez + 1];
+                            }
+#pragma unroll
+                            for (int ez = 0; ez < B1Z; ez += 2) {
+                                const float p2 = fmaf(dd[ez + 1], dd[ez + 1], dd[ez + 2] * dd[ez + 2]);
+                                pz[s][ez] = fmaf(dd[ez], dd[ez], p2);
+                                pz[s][ez + 1] = fmaf(dd[ez + 3], dd[ez + 3], p2);
+                            }
+                        }
+                        float D[B1X][B1Z];
+#pragma unroll
+                        for (int ez = 0; ez < B1Z; ++ez) {
+                            const float p12 = pz[1][ez] + pz[2][ez];
+                            D[0][ez] = pz[0][ez] + p12;
+                            D[1][ez] = p12 + pz[3][ez];
+                            D[2][ez] = (pz[2][ez] + pz[3][ez]) + pz[4][ez];
+                        }
+                        float Dy[B1X][B1Z];
+#pragma unroll
+                        for (int ex = 0; ex < B1X; ++ex)
+#pragma unroll
+                            for (int ez = 0; ez < B1Z; ++ez)
+                                Dy[ex][ez] = from_below(D[ex][ez]) + D[ex][ez];
+#pragma unroll
+                        for (int ex = 0; ex < B1X; ++ex)
+#pragma unroll
+                            for (int ez = 0; ez < B1Z; ++ez)
+                                D[ex][ez] = Dy[ex][ez] + from_above(D[ex][ez]);
+                        float gvv[B1X][B1Z];
+#pragma unroll
+                        for (int ex = 0; ex < B1X; ++ex)
+#pragma unroll
+                            for (int ez = 0; ez < B1Z; ++ez) {
+                                const float w1 = __builtin_amdgcn_exp2f(fmaf(D[ex][ez], -c2, L1[ex][ez]));
+                                const float w2 = __builtin_amdgcn_exp2f(fmaf(D[ex][ez], -c2, sl[ex][ez]));
+                                const float r = rc[ex][ez];
+                                const float r2 = r * r;
+                                float gv = fmaf(w2, r2 - se[ex][ez], w1 * (r2 - e1[ex][ez]));
+                                float wr = (w1 + w2) * r;
+                                if (bord) {
+                                    const int vx = X0 - 2 + ex0 + ex, vz = Z0 - 2 + ez0 + ez;
+                                    const bool ok = ((unsigned)y < (unsigned)ny) &
+                                                    ((unsigned)(y + dy) < (unsigned)ny) &
+                                                    ((unsigned)vx < (unsigned)nx) &
+                                                    ((unsigned)(vx + dx) < (unsigned)nx) &
+                                                    ((unsigned)vz < (unsigned)nz) &
+                                                    ((unsigned)(vz + dz) < (unsigned)nz);
+                                    gv = ok ? gv : 0.f;
+                                    wr = ok ? wr : 0.f;
+                                }
+                                gvv[ex][ez] = gv;
+                                gi[ex][ez] += wr;
+                            }
+                        if (!want_u)
+                            continue;
+                        // every wave has read the previous pair's Gv field by
+                        // now: the long stage-1 arithmetic above ran between
+                        // its stage 2 and this barrier
+                        __syncthreads();
+                        const int grow = (l >= 1 && l <= 30) ? l - 1 : 30;
+                        float *gwr = sG + grow * L::RG + ex0 * GZ + ez0;
+#pragma unroll
+                        for (int ex = 0; ex < B1X; ++ex)
+#pragma unroll
+                            for (int ez = 0; ez < B1Z; ++ez)
+                                gwr[ex * GZ + ez] = gvv[ex][ez];
+                    }
+                    __syncthreads();
+                    // ---- stage 2: box sums of Gv onto this segment's outputs
+                    if (has2) {
+                        const int grow = l < 1 ? 0 : (l > 30 ? 29 : l - 1);
+                        lds_float *bg = lds_base(sG + grow * L::RG + oz0);
+                        lds_float *bu = lds_base(sU + (l + M + dy) * L::RU + 2 * L::UZ + oz0 + 2 + M + dz);
+                        float gv[GX][B2Z + 2], ub[B2X][B2Z];
+#pragma unroll
+                        for (int ex = 0; ex < GX; ++ex)
+#pragma unroll
+                            for (int c = 0; c < B2Z + 2; ++c)
+                                gv[ex][c] = bg[ex * GZ + c];
+#pragma unroll
+                        for (int xo = 0; xo < B2X; ++xo)
+#pragma unroll
+                            for (int zo = 0; zo < B2Z; ++zo)
+                                ub[xo][zo] = bu[xo * L::UZ + zo];
+                        __builtin_amdgcn_sched_barrier(0);
+                        float gz[GX][B2Z];
+#pragma unroll
+                        for (int ex = 0; ex < GX; ++ex) {
+                            const float p12 = gv[ex][1] + gv[ex][2];
+                            gz[ex][0] = gv[ex][0] + p12;
+                            gz[ex][1] = p12 + gv[ex][3];
+                        }
+                        float gx[B2X][B2Z], gyb[B2X][B2Z];
+#pragma unroll
+                        for (int xo = 0; xo < B2X; xo += 2)
+#pragma unroll
+                            for (int zo = 0; zo < B2Z; ++zo) {
+                                const float p12 = gz[xo + 1][zo] + gz[xo + 2][zo];
+                                gx[xo][zo] = gz[xo][zo] + p12;
+                                gx[xo + 1][zo] = p12 + gz[xo + 3][zo];
+                            }
+#pragma unroll
+                        for (int xo = 0; xo < B2X; ++xo)
+#pragma unroll
+                            for (int zo = 0; zo < B2Z; ++zo)
+                                gyb[xo][zo] = from_below(gx[xo][zo]) + gx[xo][zo];
+#pragma unroll
+                        for (int xo = 0; xo < B2X; ++xo)
+#pragma unroll
+                            for (int zo = 0; zo < B2Z; ++zo) {
+                                const float G3 = gyb[xo][zo] + from_above(gx[xo][zo]);
+                                gw[xo][zo] = fmaf(uk2[xo][zo] - ub[xo][zo], G3, gw[xo][zo]);
+                            }
+                    }
+                }
+            }
+        };
+        if (border)
+            sweep(std::true_type{});
+        else
+            sweep(std::false_type{});
+    }
+
+    // writes: weight part at the padded outputs, image part at the grid
+    // voxels of this tile (Gv positions 1..4 in x, lanes 2..29, 1..30 in z)
+    const float sw = -0.5f * g.inv2h2;
+    const int64_t NP = (int64_t)(nx + 2) * (ny + 2) * (nz + 2);
+    const int Yp = y + 1;
+    const bool lrow = l >= 2 && l <= TY + 1 && Yp < ny + 2;
+    if (has2 && gpad) {
+#pragma unroll
+        for (int xo = 0; xo < B2X; ++xo)
+#pragma unroll
+            for (int zo = 0; zo < B2Z; ++zo) {
+                const int Xp = X0 + xo, Zp = Z0 + oz0 + zo;
+                if (lrow && Xp < nx + 2 && Zp < nz + 2)
+                    gpad[(int64_t)k * NP + ((int64_t)Xp * (ny + 2) + Yp) * (nz + 2) + Zp] = sw * gw[xo][zo];
+            }
+    }
+    if (a.grad_f) {
+#pragma unroll
+        for (int ex = 0; ex < B1X; ++ex)
+#pragma unroll
+            for (int ez = 0; ez < B1Z; ++ez) {
+                const int e_x = ex0 + ex, e_z = ez0 + ez;
+                const int xg = X0 - 2 + e_x, zg = Z0 - 2 + e_z;
+                if (e_x >= 1 && e_x <= TX && e_z >= 1 && e_z <= TZ && lrow &&
+                    (unsigned)xg < (unsigned)nx && (unsigned)y < (unsigned)ny &&
+                    (unsigned)zg < (unsigned)nz)
+                    a.grad_f[vox(k, xg, y, zg)] = 0.5f * gi[ex][ez];
+            }
+    }
+}
+
+Grid grid_for(const Geo &g)
+{
+    Grid gg;
+    gg.ntx = (g.nx + 2 + TX - 1) / TX;
+    gg.nty = (g.ny + 2 + TY - 1) / TY;
+    gg.ntz = (g.nz + 2 + TZ - 1) / TZ;
+    gg.nblocks = g.np * gg.ntx * gg.nty * gg.ntz;
+    return gg;
+}
+
+template <typename T, int M>
+void launch(const Geo &g, const GradArgs &a, float *gpad, hipStream_t s)
+{
+    const Grid gg = grid_for(g);
+    grad_lds_kernel<T, M><<<gg.nblocks, THREADS, 0, s>>>(g, a, gpad, gg);
+}
+
+template <typename T>
+void launch_m(const Geo &g, const GradArgs &a, float *gpad, hipStream_t s)
+{
+    switch (g.M) {
+    case 1:
+        launch<T, 1>(g, a, gpad, s);
+        break;
+    case 2:
+        launch<T, 2>(g, a, gpad, s);
+        break;
+    case 3:
+        launch<T, 3>(g, a, gpad, s);
+        break;
+    default:
+        launch<T, 4>(g, a, gpad, s);
+        break;
+    }
+}
+}  // namespace v2
+
 GradGrid grad_grid(const Geo &g, int tz)
 {
     GradGrid gg;
@@ -514,12 +919,15 @@ void launch_m(const Geo &g, const GradArgs &a, float *gpad, hipStream_t s)
 template <typename T>
 hipError_t launch_t(const Geo &g, const GradArgs &a, float *gpad, hipStream_t s)
 {
-    if (a.u == a.f)
+    if (a.u == a.f && g.M <= v2::kMaxM)
+        v2::launch_m<T>(g, a, gpad, s);
+    else if (a.u == a.f)
         launch_m<T, true>(g, a, gpad, s);
     else
         launch_m<T, false>(g, a, gpad, s);
     return hipGetLastError();
 }
+
 
 }  // namespace
 
