@@ -229,3 +229,136 @@ def quantise(x, storage):
         raw = to_bf16_bits(x)
         return bf16_bits_to_f32(raw).astype(np.float64), raw
     raise ValueError(storage)
+
+
+# ----------------------------------------------------------------------------
+# Cone-beam data for the reconstruction workload (Sec. 2.5, scaled): the
+# breathing phantom's projections taken analytically from its ellipsoids, so
+# the data are not produced by the discrete projector that reconstructs them.
+# Geometry: voxel units, isocentre at the volume centre; for gantry angle t
+# the source is at sid (cos t, sin t, 0), the flat detector perpendicular to
+# the central ray at sdd from the source, pixel (iu, iv) centred at
+# (iu - (nu-1)/2) du along (-sin t, cos t, 0) and (iv - (nv-1)/2) dv along z.
+# ----------------------------------------------------------------------------
+
+
+@dataclasses.dataclass(frozen=True)
+class CTWorkload:
+    name: str
+    np_: int
+    nx: int
+    ny: int
+    nz: int
+    nu: int
+    nv: int
+    na: int          # angles per phase
+    sid: float
+    sdd: float
+    du: float
+    dv: float
+    lesion_r: float
+    amp: float
+    noise: float     # relative Gaussian noise of the projections
+    seed: int
+
+
+CT_WORKLOADS = {
+    # 10 phases of 64^3 voxels; 300 projections over 360 degrees binned into
+    # 10 phases (30 each, interleaved); source-isocentre and source-detector
+    # distances in the ratio 100 : 153.6 of the paper's geometry
+    "recon64": CTWorkload("recon64", 10, 64, 64, 64, 128, 96, 30, 250.0, 384.0,
+                          1.2, 1.2, 6.0, 3.0, 0.0, 1201 + 5),
+}
+
+
+def ct_angles(np_, na, total=None):
+    """Gantry angles (np_, na): `total` = np_ * na projections equally spaced
+    over 360 degrees, projection k going to phase k mod np_ (a regular
+    breathing pattern sampled at a constant rate)."""
+    total = np_ * na if total is None else total
+    k = np.arange(np_ * na).reshape(na, np_).T  # phase i: k = i, i + np_, ...
+    return 2.0 * math.pi * k / total
+
+
+def _ray_ellipsoid_chord(S, D, centre, axes):
+    """Chord length of the lines S + t D (arrays (..., 3)) through an
+    ellipsoid."""
+    q = (S - centre) / axes
+    e = D / axes
+    A = np.sum(e * e, axis=-1)
+    B = 2.0 * np.sum(q * e, axis=-1)
+    C = np.sum(q * q, axis=-1) - 1.0
+    disc = B * B - 4.0 * A * C
+    dt = np.sqrt(np.maximum(disc, 0.0)) / A
+    return np.where(disc > 0.0, dt * np.linalg.norm(D, axis=-1), 0.0)
+
+
+def analytic_projections(w: CTWorkload, angles=None):
+    """Line integrals of the clean phantom of every phase along every ray,
+    from the ellipsoids themselves: torso 0.2, lungs 0.02 inside it, lesion
+    0.25 inside the +x lung, so the image is 0.2 T - 0.18 (L1 + L2) +
+    0.23 S. Returns (np_, na, nu, nv) float64."""
+    angles = ct_angles(w.np_, w.na) if angles is None else angles
+    nx, ny, nz = w.nx, w.ny, w.nz
+    out = np.empty((w.np_, w.na, w.nu, w.nv))
+    ou = (np.arange(w.nu) - 0.5 * (w.nu - 1)) * w.du
+    ov = (np.arange(w.nv) - 0.5 * (w.nv - 1)) * w.dv
+    for i in range(w.np_):
+        lz = w.amp * math.sin(2.0 * math.pi * i / w.np_)
+        shapes = [((0.0, 0.0, 0.0), (0.45 * nx, 0.35 * ny, 0.45 * nz), 0.2),
+                  ((0.2 * nx, 0.0, 0.0), (0.14 * nx, 0.2 * ny, 0.35 * nz), -0.18),
+                  ((-0.2 * nx, 0.0, 0.0), (0.14 * nx, 0.2 * ny, 0.35 * nz), -0.18),
+                  ((0.2 * nx, 0.0, lz), (w.lesion_r,) * 3, 0.23)]
+        for a in range(w.na):
+            t = angles[i, a]
+            c, s = math.cos(t), math.sin(t)
+            S = np.array([w.sid * c, w.sid * s, 0.0])
+            P = np.empty((w.nu, w.nv, 3))
+            P[..., 0] = S[0] - w.sdd * c - ou[:, None] * s
+            P[..., 1] = S[1] - w.sdd * s + ou[:, None] * c
+            P[..., 2] = ov[None, :]
+            D = P - S
+            acc = np.zeros((w.nu, w.nv))
+            for centre, axes, val in shapes:
+                acc += val * _ray_ellipsoid_chord(S, D, np.array(centre), np.array(axes))
+            out[i, a] = acc
+    if w.noise > 0:
+        rng = np.random.Generator(np.random.PCG64(w.seed))
+        out = out + rng.normal(0.0, w.noise, size=out.shape) * np.abs(out)
+    return out
+
+
+def ct_clean_volumes(w: CTWorkload):
+    """The voxelised clean phantom of every phase (the reconstruction's
+    ground truth), float64 (np_, nx, ny, nz)."""
+    return np.stack([clean_phase(w.nx, w.ny, w.nz, i, w.np_, w.lesion_r, w.amp)
+                     for i in range(w.np_)])
+
+
+def ray_geometry(w, angles):
+    """Source points S (np_, na, 3) and ray directions D (np_, na, nu, nv, 3)
+    from the source to every pixel centre (the geometry above)."""
+    ou = (np.arange(w.nu) - 0.5 * (w.nu - 1)) * w.du
+    ov = (np.arange(w.nv) - 0.5 * (w.nv - 1)) * w.dv
+    c, s = np.cos(angles), np.sin(angles)
+    S = np.stack([w.sid * c, w.sid * s, np.zeros_like(c)], axis=-1)
+    D = np.empty(angles.shape + (w.nu, w.nv, 3))
+    D[..., 0] = (-w.sdd * c)[..., None, None] - ou[None, None, :, None] * s[..., None, None]
+    D[..., 1] = (-w.sdd * s)[..., None, None] + ou[None, None, :, None] * c[..., None, None]
+    D[..., 2] = np.broadcast_to(ov, D.shape[:-1])
+    return S, D
+
+
+def box_projections(w, angles, lo, hi, value=1.0):
+    """value x the length of every ray inside the axis-aligned box [lo, hi]
+    (voxel units, isocentre at the origin), by slab clipping."""
+    S, D = ray_geometry(w, angles)
+    S = S[:, :, None, None, :]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        t0 = (np.asarray(lo) - S) / D
+        t1 = (np.asarray(hi) - S) / D
+    inside = (S >= np.asarray(lo)) & (S <= np.asarray(hi))
+    tmin = np.where(D == 0, np.where(inside, -np.inf, np.inf), np.minimum(t0, t1))
+    tmax = np.where(D == 0, np.where(inside, np.inf, -np.inf), np.maximum(t0, t1))
+    tin, tout = tmin.max(axis=-1), tmax.min(axis=-1)
+    return value * np.maximum(tout - tin, 0.0) * np.linalg.norm(D, axis=-1)

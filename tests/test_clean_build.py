@@ -34,6 +34,7 @@ def test_build_from_a_clean_checkout(tmp_path):
                        cwd=dst, capture_output=True, text=True, timeout=900)
     assert r.returncode == 0, r.stdout[-2000:] + r.stderr[-4000:]
     assert lib.exists() and (dst / "oracle" / "libtnlm_oracle.so").exists()
+    assert (dst / "oracle" / "libct_oracle.so").exists()
     assert "tnlm" in r.stdout
     r = subprocess.run([sys.executable, "-c",
                         "from paper_1201_2450_amd import _lib;"

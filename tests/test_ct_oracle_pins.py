@@ -1,0 +1,128 @@
+"""Pins of the reconstruction oracle (oracle/ct.py, ct_oracle.c), CPU.
+
+  * a voxel-aligned, off-centre box projects to its exact chord lengths,
+    computed independently from the geometry's definition (slab clipping in
+    phantom.box_projections): pins the source side, the detector axes, the
+    angle sense, the candidate enumeration and every length;
+  * <P x, y> = <x, P^T y> for random x, y: pins the transpose's indexing;
+  * the voxelised breathing phantom's projections approach the analytic line
+    integrals of its ellipsoids as the voxels shrink (first order);
+  * CGLS iterate k is the minimiser of ||P x - y|| over x0 + the Krylov space
+    K_k(P^T P, P^T r0), computed densely; its residual never grows;
+  * TNLM-R keeps a positive constant volume with consistent data fixed, and
+    its output is never negative.
+"""
+import numpy as np
+import pytest
+
+from oracle import ct
+from phantom.breathing import (CTWorkload, analytic_projections, box_projections,
+                               ct_angles, ct_clean_volumes)
+
+
+def small(n=12, nu=20, nv=16, na=5, np_=2):
+    s = n / 32
+    w = CTWorkload("t", np_, n, n, n, nu, nv, na, 125.0 * s, 192.0 * s, 1.3 * s, 1.3 * s,
+                   2.0 * s, 1.0 * s, 0.0, 7)
+    g = ct.CTGeom(np_, n, n, n, nu, nv, na, w.sid, w.sdd, w.du, w.dv)
+    return w, g
+
+
+@pytest.mark.parametrize("shape", [(12, 12, 12), (9, 14, 7)])
+def test_voxel_aligned_box_projects_to_its_chords(shape):
+    nx, ny, nz = shape
+    w = CTWorkload("t", 2, nx, ny, nz, 24, 18, 7, 40.0, 64.0, 1.1, 0.9, 1.0, 1.0, 0.0, 7)
+    g = ct.CTGeom(2, nx, ny, nz, w.nu, w.nv, w.na, w.sid, w.sdd, w.du, w.dv)
+    rng = np.random.default_rng(3)
+    ang = rng.uniform(0, 2 * np.pi, size=(2, w.na))
+    ang[0, 0], ang[0, 1], ang[1, 0] = 0.0, np.pi / 2, np.pi  # axis-aligned rays too
+    c = np.array([(nx - 1) / 2, (ny - 1) / 2, (nz - 1) / 2])
+    ix, iy, iz = (2, nx - 3), (1, 4), (nz - 4, nz - 2)   # voxel index ranges
+    vol = np.zeros((2, nx, ny, nz))
+    vol[:, ix[0]:ix[1] + 1, iy[0]:iy[1] + 1, iz[0]:iz[1] + 1] = 0.7
+    lo = np.array([ix[0], iy[0], iz[0]]) - c - 0.5
+    hi = np.array([ix[1], iy[1], iz[1]]) - c + 0.5
+    want = box_projections(w, ang, lo, hi, 0.7)
+    got = ct.project(g, ang, vol)
+    assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
+    assert (want > 0).sum() > 100  # the box is seen by many rays
+
+
+def test_transpose_is_the_adjoint():
+    w, g = small(10, 18, 14, 6, 3)
+    rng = np.random.default_rng(4)
+    ang = rng.uniform(0, 2 * np.pi, size=(3, 6))
+    x = rng.normal(size=g.vol_shape)
+    y = rng.normal(size=g.proj_shape)
+    lhs = np.vdot(ct.project(g, ang, x), y)
+    rhs = np.vdot(x, ct.backproject(g, ang, y))
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+def test_voxelised_phantom_converges_to_the_analytic_projections():
+    errs = []
+    for n in (16, 32, 64):
+        s = n / 32
+        w = CTWorkload("t", 1, n, n, n, 48, 36, 3, 125.0 * s, 192.0 * s, 1.6 * s,
+                       1.6 * s, 3.0 * s, 1.5 * s, 0.0, 7)
+        g = ct.CTGeom(1, n, n, n, w.nu, w.nv, w.na, w.sid, w.sdd, w.du, w.dv)
+        ang = ct_angles(1, w.na)
+        y = analytic_projections(w, ang)
+        p = ct.project(g, ang, ct_clean_volumes(w))
+        errs.append(np.sqrt(np.mean((p - y) ** 2) / np.mean(y ** 2)))
+    # voxelising sharp edges: an error of first order in the voxel size
+    assert errs[1] < 0.65 * errs[0] and errs[2] < 0.65 * errs[1], errs
+    assert errs[2] < 0.05
+
+
+def _dense(g, ang):
+    """P as a dense matrix per phase, column by column from unit volumes."""
+    N = g.nx * g.ny * g.nz
+    R = g.na * g.nu * g.nv
+    A = np.zeros((g.np_, R, N))
+    for v in range(N):
+        e = np.zeros(g.vol_shape)
+        e[:, v // (g.ny * g.nz), (v // g.nz) % g.ny, v % g.nz] = 1.0
+        A[:, :, v] = ct.project(g, ang, e).reshape(g.np_, R)
+    return A
+
+
+def test_cgls_iterates_are_the_krylov_least_squares_minimisers():
+    w, g = small(5, 10, 8, 4, 2)
+    ang = ct_angles(2, 4)
+    rng = np.random.default_rng(5)
+    y = rng.uniform(0.5, 1.5, size=g.proj_shape)
+    x0 = rng.uniform(0.0, 0.2, size=g.vol_shape)
+    A = _dense(g, ang)
+    st = ct.cgls_init(g, ang, y, x0)
+    res = [np.linalg.norm((A @ st.x.reshape(2, -1, 1))[..., 0] - y.reshape(2, -1), axis=1)]
+    for k in range(1, 6):
+        st = ct.cgls_step(g, ang, st)
+        for i in range(2):
+            Ai, bi, xi0 = A[i], y[i].ravel(), x0[i].ravel()
+            r0 = bi - Ai @ xi0
+            # Krylov basis of A^T A started at A^T r0, orthonormalised
+            K = [Ai.T @ r0]
+            for _ in range(k - 1):
+                K.append(Ai.T @ (Ai @ K[-1]))
+            Q, _ = np.linalg.qr(np.stack(K, axis=1))
+            c, *_ = np.linalg.lstsq(Ai @ Q, r0, rcond=None)
+            want = xi0 + Q @ c
+            got = st.x[i].ravel()
+            assert np.abs(got - want).max() <= 1e-8 * np.abs(want).max(), (k, i)
+        res.append(np.linalg.norm((A @ st.x.reshape(2, -1, 1))[..., 0] - y.reshape(2, -1), axis=1))
+    res = np.array(res)
+    assert np.all(np.diff(res, axis=0) <= 1e-12 * res[0])
+
+
+def test_tnlm_r_fixed_point_and_positivity():
+    w, g = small(8, 16, 12, 4, 3)
+    ang = ct_angles(3, 4)
+    c = np.full(g.vol_shape, 0.3)
+    y = ct.project(g, ang, c)
+    f = ct.tnlm_r(g, ang, y, c, 0.5, 1, 1, 0.05, outer=2, cg_iters=3)
+    assert np.abs(f - 0.3).max() <= 1e-12
+    rng = np.random.default_rng(6)
+    y2 = y + rng.normal(0, 0.5, size=y.shape)
+    f2 = ct.tnlm_r(g, ang, y2, np.zeros(g.vol_shape), 0.5, 1, 1, 0.05, outer=2, cg_iters=3)
+    assert f2.min() >= 0.0 and f2.max() > 0.0
