@@ -213,6 +213,51 @@ def regulariser(args, w, dev):
         "breakdown_ms": ms, "roofline": roofline, "cpu_baseline": cpu}), flush=True)
 
 
+def reconstruction(name, dev, cg_iters=10, reps=2):
+    """One outer iteration of the TNLM-R algorithm on a cone-beam workload:
+    cg_iters CGLS iterations of (P1) for all phases, one Gauss-Jacobi step
+    (weights from the CGLS result, window 5^3, patch 3^3) and positivity;
+    plus the projector and its transpose alone. Returns the timings (ms)."""
+    import numpy as np
+    import torch
+
+    import paper_1201_2450_amd as tnlm
+    from phantom.breathing import CT_WORKLOADS, analytic_projections, ct_angles
+
+    w = CT_WORKLOADS[name]
+    geo = tnlm.ct.Geometry(w.nu, w.nv, w.sid, w.sdd, w.du, w.dv)
+    ang = np.ascontiguousarray(ct_angles(w.np_, w.na), dtype=np.float32)
+    at = torch.from_numpy(ang).to(dev)
+    log(f"{name}: analytic projections {(w.np_, w.na, w.nu, w.nv)} ...")
+    y = torch.from_numpy(analytic_projections(w, ang.astype(np.float64)).astype(np.float32)).to(dev)
+    shape = (w.np_, w.nx, w.ny, w.nz)
+    f = torch.zeros(shape, dtype=torch.float32, device=dev)
+    EV = lambda: torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = EV(), EV()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    q = tnlm.ct.project(f + 0.1, geo, at)
+    proj_ms = timed(lambda: tnlm.ct.project(f, geo, at, out=q))
+    bp = torch.empty_like(f)
+    back_ms = timed(lambda: tnlm.ct.backproject(y, geo, at, shape, out=bp))
+    outer_ms = timed(lambda: tnlm.ct.reconstruct(y, geo, at, f, mu=0.5, d=1, M=2, h=0.05,
+                                                 outer=1, cg_iters=cg_iters))
+    return {"workload": name, "phases": w.np_, "grid": [w.nx, w.ny, w.nz],
+            "detector": [w.nu, w.nv], "angles_per_phase": w.na,
+            "project_ms": proj_ms, "backproject_ms": back_ms,
+            "tnlm_r_outer_iteration_ms": outer_ms, "cg_iterations": cg_iters,
+            "rays_per_s_project": w.np_ * w.na * w.nu * w.nv / (proj_ms / 1e3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -236,8 +281,18 @@ def main():
     import paper_1201_2450_amd as tnlm
     from phantom import WORKLOADS, workload_inputs
 
-    w = WORKLOADS[args.workload]
     dev = torch.device("cuda", 0)
+    if args.workload.startswith("recon"):
+        # the reconstruction model alone (not the default): timings only
+        r = reconstruction(args.workload, dev)
+        print(json.dumps({"metric": "TNLM-R outer iteration ms (CGLS + Eq. 8 + positivity)",
+                          "value": r["tnlm_r_outer_iteration_ms"], "unit": "ms",
+                          "higher_is_better": False, "n_gpus": 1, "dtype": "f32",
+                          "data": "synthetic", "config": {"workload": args.workload},
+                          "breakdown": r, "roofline": None, "cpu_baseline": None,
+                          "vs_baseline": None}), flush=True)
+        return
+    w = WORKLOADS[args.workload]
     if w.mu is None:
         return regulariser(args, w, dev)
     log(f"generating {w.name} {w.shape} ...")
@@ -438,6 +493,11 @@ def main():
                                  shape=list(we.shape), window=2 * we.M + 1)
         del fe
 
+    recon = None
+    if not args.no_dtypes:
+        log("timing one TNLM-R outer iteration (reconstruction model) ...")
+        recon = reconstruction("recon64", dev)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on a sample ...")
@@ -458,6 +518,7 @@ def main():
         "jacobi_voxel_updates_per_s": nvox / (ms["jacobi"] / 1e3),
         "storage_dtypes": dtypes,
         "autograd": autograd,
+        "reconstruction": recon,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "paper_context": {"tnlm_e_per_iteration_s": 55.07,

@@ -200,6 +200,75 @@ const char *tnlm_strerror(int code);
 /* tnlm_version — library version string, e.g. "tnlm 0.1 gfx950". */
 const char *tnlm_version(void);
 
+/* ------------------------------------------------------------------------
+ * Reconstruction model: the data-fidelity part of Eq. (1) and the (P1)
+ * sub-problem of Eq. (5), solved by CGLS phase by phase (Sec. 2.3), for the
+ * TNLM-R algorithm (Sec. 2.3): (P1) by CGLS, weights and one Eq. (8) step
+ * from its result (tnlm_jacobi_step), then positivity (tnlm_clamp_nonneg).
+ *
+ * Projection matrix P_i of phase i: (P f)_r = sum_v a_{r,v} f_v with a_{r,v}
+ * the length of ray r inside voxel v, i.e. the line integral of the image
+ * taken as constant over unit voxel cubes centred on the grid points.
+ * Geometry (circular cone beam, Sec. 2.5), lengths in voxel units, isocentre
+ * at the volume centre c = ((nx-1)/2, (ny-1)/2, (nz-1)/2): for gantry angle
+ * t the source is at S = sid (cos t, sin t, 0); the flat detector is
+ * perpendicular to the central ray at distance sdd from the source; pixel
+ * (iu, iv) is centred at S + sdd (-cos t, -sin t, 0)
+ * + (iu - (nu-1)/2) du (-sin t, cos t, 0) + (iv - (nv-1)/2) dv (0, 0, 1);
+ * ray r is the line through S and that pixel centre.
+ * Layouts: volumes [np][nx][ny][nz] FP32 (z fastest); projections
+ * [np][na][nu][nv] FP32 (v fastest); angles [np][na] FP32 radians, device.
+ * ------------------------------------------------------------------------ */
+typedef struct tnlm_ct_geom {
+    int32_t np;            /* phases (each with its own angles), >= 1        */
+    int32_t nx, ny, nz;    /* volume grid                                   */
+    int32_t nu, nv;        /* detector pixels (u in the gantry plane, v = z) */
+    int32_t na;            /* projection angles per phase                   */
+    float sid, sdd;        /* source-isocentre, source-detector distances   */
+    float du, dv;          /* detector pixel pitch at the detector          */
+    const float *angles;   /* device [np][na], radians                      */
+} tnlm_ct_geom;
+/* Limits: every size >= 1; np*nx*ny*nz and np*na*nu*nv < 2^31; sid, sdd,
+ * du, dv finite and > 0; the source and the detector outside the volume:
+ * sid and sdd - sid larger than the volume's half-diagonal in the gantry
+ * plane (TNLM_EINVAL otherwise). */
+
+/* tnlm_ct_project — proj = P vol for every phase (Eq. (1)). vol and proj
+ * must not overlap. */
+int tnlm_ct_project(const tnlm_ct_geom *geom, const float *vol, float *proj, void *stream);
+
+/* tnlm_ct_backproject — vol = P^T proj for every phase: the transpose of
+ * tnlm_ct_project (same lengths a_{r,v}), gathered per voxel. */
+int tnlm_ct_backproject(const tnlm_ct_geom *geom, const float *proj, float *vol,
+                        void *stream);
+
+/* tnlm_ct_workspace_bytes — device workspace of the CGLS calls (host call);
+ * (size_t)-1 for an invalid geometry. Layout (floats, then pairs of floats
+ * hi, lo whose sum is the value): r [np][na*nu*nv] at offset 0, then
+ * q [np][na*nu*nv], p [np][N], s [np][N] (N = nx*ny*nz), then gamma [np],
+ * qq [np], gnew [np] as pairs, then partial sums. */
+size_t tnlm_ct_workspace_bytes(const tnlm_ct_geom *geom);
+
+/* tnlm_cgls_init — starts CGLS for min_g sum_i ||P_i g_i - y_i||^2 ((P1) of
+ * Eq. (5)) from x (Sec. 2.3: the previous iterate): r = y - P x,
+ * s = P^T r, p = s, gamma = |s|^2 per phase, all in ws (layout above).
+ * y [np][na][nu][nv]; x [np][nx][ny][nz] (read). */
+int tnlm_cgls_init(const tnlm_ct_geom *geom, const float *y, const float *x, void *ws,
+                   size_t ws_bytes, void *stream);
+
+/* tnlm_cgls_step — iters CGLS iterations on the state in ws, updating x in
+ * place (x must be the volume tnlm_cgls_init started from, or its result):
+ * q = P p, alpha = gamma/|q|^2, x += alpha p, r -= alpha q, s = P^T r,
+ * gnew = |s|^2, p = s + (gnew/gamma) p, gamma = gnew; per phase, every
+ * scalar on the device (a phase whose |q|^2 or gamma is 0 takes a zero
+ * step). Dot products are compensated sums in a fixed order. */
+int tnlm_cgls_step(const tnlm_ct_geom *geom, float *x, int iters, void *ws, size_t ws_bytes,
+                   void *stream);
+
+/* tnlm_clamp_nonneg — x = max(x, 0) elementwise over n floats (the
+ * positivity step of the TNLM-R algorithm, Sec. 2.3); NaN stays NaN. */
+int tnlm_clamp_nonneg(float *x, int64_t n, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

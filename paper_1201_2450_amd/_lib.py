@@ -30,6 +30,16 @@ class Geom(ctypes.Structure):
                 ("h", ctypes.c_float)]
 
 
+class CTGeom(ctypes.Structure):
+    """struct tnlm_ct_geom."""
+    _fields_ = [("np", ctypes.c_int32), ("nx", ctypes.c_int32),
+                ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("nu", ctypes.c_int32), ("nv", ctypes.c_int32),
+                ("na", ctypes.c_int32), ("sid", ctypes.c_float),
+                ("sdd", ctypes.c_float), ("du", ctypes.c_float),
+                ("dv", ctypes.c_float), ("angles", ctypes.c_void_p)]
+
+
 class TNLMError(RuntimeError):
     def __init__(self, code, what):
         self.code = code
@@ -54,6 +64,14 @@ def _load():
     lib.tnlm_energy.argtypes = [gp, i, vp, vp, fp, fp, vp, sz, vp]
     lib.tnlm_energy_noalloc.argtypes = [gp, i, vp, vp, fp, fp, vp]
     lib.tnlm_grad.argtypes = [gp, i, vp, vp, i, fp, fp, fp, vp, sz, vp]
+    cp = ctypes.POINTER(CTGeom)
+    lib.tnlm_ct_project.argtypes = [cp, fp, fp, vp]
+    lib.tnlm_ct_backproject.argtypes = [cp, fp, fp, vp]
+    lib.tnlm_ct_workspace_bytes.argtypes = [cp]
+    lib.tnlm_ct_workspace_bytes.restype = sz
+    lib.tnlm_cgls_init.argtypes = [cp, fp, fp, vp, sz, vp]
+    lib.tnlm_cgls_step.argtypes = [cp, fp, i, vp, sz, vp]
+    lib.tnlm_clamp_nonneg.argtypes = [fp, ctypes.c_int64, vp]
     lib.tnlm_workspace_bytes.argtypes = [gp, i]
     lib.tnlm_workspace_bytes.restype = sz
     lib.tnlm_strerror.argtypes = [i]
@@ -61,7 +79,9 @@ def _load():
     lib.tnlm_version.argtypes = []
     lib.tnlm_version.restype = ctypes.c_char_p
     for name in ("tnlm_weights", "tnlm_jacobi_step", "tnlm_energy",
-                 "tnlm_energy_noalloc", "tnlm_grad"):
+                 "tnlm_energy_noalloc", "tnlm_grad", "tnlm_ct_project",
+                 "tnlm_ct_backproject", "tnlm_cgls_init", "tnlm_cgls_step",
+                 "tnlm_clamp_nonneg"):
         getattr(lib, name).restype = ctypes.c_int
     return lib
 

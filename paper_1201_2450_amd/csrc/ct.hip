@@ -1,0 +1,431 @@
+// Reconstruction model kernels (Eq. (1), (P1) of Eq. (5)): the cone-beam
+// projector P of every phase, its transpose, and the CGLS iteration for the
+// per-phase least-squares problem, with every scalar kept on the device.
+//
+// P: a_{r,v} = length of ray r inside voxel v (unit cubes centred on the
+// grid points, isocentre at the volume centre). Forward: one thread per ray
+// walks the voxels it crosses in order (the next x, y and z plane crossings
+// taken from the plane index each step, so errors do not accumulate) and
+// sums length x value. Transpose: one thread per voxel and angle loop: the
+// voxel's eight corners are projected to the detector, and every pixel whose
+// centre falls in that footprint has its ray clipped against the voxel's
+// cube; length x projection value is summed. Both enumerate the same
+// (ray, voxel) pairs with the same lengths (up to rounding), in gather form:
+// no atomics, deterministic.
+//
+// Geometry (voxel units): for gantry angle t the source is at
+// sid (cos t, sin t, 0); pixel (iu, iv) is centred at
+// S + sdd (-cos t, -sin t, 0) + (iu - (nu-1)/2) du e_u + (iv - (nv-1)/2) dv e_v,
+// e_u = (-sin t, cos t, 0), e_v = (0, 0, 1). Projections [np][na][nu][nv].
+#include <math.h>
+
+#include "tnlm_internal.h"
+
+namespace tnlm {
+namespace {
+
+constexpr int kBlock = 256;
+
+struct CTG {
+    int np, nx, ny, nz, nu, nv, na;
+    float sid, sdd, du, dv;
+    const float *angles;
+    int64_t N, R;  // voxels per phase, rays per phase
+};
+
+__device__ __forceinline__ void ray_of(const CTG &g, float th, int iu, int iv, float S[3],
+                                       float d[3])
+{
+    float s, c;
+    sincosf(th, &s, &c);
+    const float ou = (iu - 0.5f * (g.nu - 1)) * g.du;
+    const float ov = (iv - 0.5f * (g.nv - 1)) * g.dv;
+    S[0] = g.sid * c;
+    S[1] = g.sid * s;
+    S[2] = 0.f;
+    d[0] = -g.sdd * c - ou * s;
+    d[1] = -g.sdd * s + ou * c;
+    d[2] = ov;
+}
+
+// parameter interval of the ray inside [lo, hi] along one axis
+__device__ __forceinline__ bool slab(float S, float d, float lo, float hi, float &t0, float &t1)
+{
+    if (d == 0.f) {
+        t0 = -INFINITY;
+        t1 = INFINITY;
+        return S >= lo && S <= hi;
+    }
+    const float inv = 1.f / d;
+    const float a = (lo - S) * inv, b = (hi - S) * inv;
+    t0 = fminf(a, b);
+    t1 = fmaxf(a, b);
+    return true;
+}
+
+__global__ void __launch_bounds__(kBlock) project_kernel(CTG g, const float *vol, float *proj)
+{
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (int64_t)g.np * g.R)
+        return;
+    const int i = (int)(t / g.R);
+    const int64_t rr = t - (int64_t)i * g.R;
+    const int a = (int)(rr / ((int64_t)g.nu * g.nv));
+    const int iu = (int)((rr / g.nv) % g.nu), iv = (int)(rr % g.nv);
+    float S[3], d[3];
+    ray_of(g, g.angles[(int64_t)i * g.na + a], iu, iv, S, d);
+    const int n[3] = {g.nx, g.ny, g.nz};
+    float c[3];
+    for (int k = 0; k < 3; ++k)
+        c[k] = 0.5f * (n[k] - 1);
+    float tin = -INFINITY, tout = INFINITY;
+    for (int k = 0; k < 3; ++k) {
+        float a0, a1;
+        if (!slab(S[k], d[k], -c[k] - 0.5f, c[k] + 0.5f, a0, a1)) {
+            proj[t] = 0.f;
+            return;
+        }
+        tin = fmaxf(tin, a0);
+        tout = fminf(tout, a1);
+    }
+    if (!(tout > tin)) {
+        proj[t] = 0.f;
+        return;
+    }
+    const float L = sqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    // voxel of the entry point, clamped to the grid (on the entry face the
+    // coordinate is at the box boundary; where it lies on a plane between two
+    // voxels either is right: the walk then takes a zero-length step)
+    int idx[3], step[3];
+    float inv[3];
+    for (int k = 0; k < 3; ++k) {
+        const float p = S[k] + tin * d[k] + c[k] + 0.5f;
+        int q = (int)floorf(p);
+        idx[k] = q < 0 ? 0 : (q > n[k] - 1 ? n[k] - 1 : q);
+        step[k] = d[k] > 0.f ? 1 : (d[k] < 0.f ? -1 : 0);
+        inv[k] = d[k] != 0.f ? 1.f / d[k] : 0.f;
+    }
+    const float *v = vol + (int64_t)i * g.N;
+    float acc = 0.f, tc = tin;
+    const int maxsteps = g.nx + g.ny + g.nz + 3;
+    for (int it = 0; it < maxsteps; ++it) {
+        // next plane crossing along each axis, from the plane index
+        float tn[3];
+        for (int k = 0; k < 3; ++k) {
+            if (step[k] == 0) {
+                tn[k] = INFINITY;
+            } else {
+                const float plane = (float)(idx[k] + (step[k] > 0 ? 1 : 0)) - 0.5f - c[k];
+                tn[k] = (plane - S[k]) * inv[k];
+            }
+        }
+        int ax = 0;
+        if (tn[1] < tn[ax])
+            ax = 1;
+        if (tn[2] < tn[ax])
+            ax = 2;
+        const float te = fminf(tn[ax], tout);
+        if (te > tc)
+            acc = fmaf((te - tc) * L, v[((int64_t)idx[0] * g.ny + idx[1]) * g.nz + idx[2]], acc);
+        if (te >= tout)
+            break;
+        tc = te;
+        idx[ax] += step[ax];
+        if (idx[ax] < 0 || idx[ax] >= n[ax])
+            break;
+    }
+    proj[t] = acc;
+}
+
+__global__ void __launch_bounds__(kBlock) backproject_kernel(CTG g, const float *proj, float *vol)
+{
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= (int64_t)g.np * g.N)
+        return;
+    const int i = (int)(t / g.N);
+    const int64_t vv = t - (int64_t)i * g.N;
+    const int z = (int)(vv % g.nz), y = (int)((vv / g.nz) % g.ny), x = (int)(vv / ((int64_t)g.nz * g.ny));
+    const float cen[3] = {x - 0.5f * (g.nx - 1), y - 0.5f * (g.ny - 1), z - 0.5f * (g.nz - 1)};
+    const float ucen = 0.5f * (g.nu - 1), vcen = 0.5f * (g.nv - 1);
+    float acc = 0.f;
+    for (int a = 0; a < g.na; ++a) {
+        const float th = g.angles[(int64_t)i * g.na + a];
+        float s, c;
+        sincosf(th, &s, &c);
+        // footprint: the corners projected onto the detector (pixel units)
+        float umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY;
+        for (int k = 0; k < 8; ++k) {
+            const float X = cen[0] + ((k & 1) ? 0.5f : -0.5f);
+            const float Y = cen[1] + ((k & 2) ? 0.5f : -0.5f);
+            const float Z = cen[2] + ((k & 4) ? 0.5f : -0.5f);
+            const float w = g.sid - (X * c + Y * s);  // depth from the source
+            const float m = g.sdd / w;
+            const float u = (-X * s + Y * c) * m / g.du + ucen;
+            const float vz = Z * m / g.dv + vcen;
+            umin = fminf(umin, u);
+            umax = fmaxf(umax, u);
+            vmin = fminf(vmin, vz);
+            vmax = fmaxf(vmax, vz);
+        }
+        // clamped in float before converting (the depth w stays above zero:
+        // the source lies outside the volume)
+        const int u0 = (int)fmaxf(0.f, ceilf(umin)), u1 = (int)fminf(g.nu - 1.f, floorf(umax));
+        const int v0 = (int)fmaxf(0.f, ceilf(vmin)), v1 = (int)fminf(g.nv - 1.f, floorf(vmax));
+        const float *pa = proj + ((int64_t)i * g.na + a) * g.nu * g.nv;
+        for (int iu = u0; iu <= u1; ++iu)
+            for (int iv = v0; iv <= v1; ++iv) {
+                float S[3], d[3];
+                ray_of(g, th, iu, iv, S, d);
+                float tin = -INFINITY, tout = INFINITY;
+                bool hit = true;
+                for (int k = 0; k < 3; ++k) {
+                    float a0, a1;
+                    const bool in = slab(S[k], d[k], cen[k] - 0.5f, cen[k] + 0.5f, a0, a1);
+                    hit = hit && in;
+                    tin = fmaxf(tin, a0);
+                    tout = fminf(tout, a1);
+                }
+                if (hit && tout > tin) {
+                    const float L = sqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+                    acc = fmaf((tout - tin) * L, pa[(int64_t)iu * g.nv + iv], acc);
+                }
+            }
+    }
+    vol[t] = acc;
+}
+
+// ---- CGLS (per phase, scalars on the device) ------------------------------
+// Workspace: r [np][R], q [np][R], p [np][N], s [np][N] (floats), then the
+// per-phase scalars gamma, qq, gnew (compensated pairs), then the partial
+// sums of the dot products.
+constexpr int kDotBlocks = 64;  // partial sums per phase
+
+__global__ void __launch_bounds__(kBlock) sub_kernel(int64_t n, const float *a, const float *b,
+                                                     float *out)
+{
+    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * kBlock)
+        out[t] = a[t] - b[t];
+}
+
+__global__ void __launch_bounds__(kBlock) copy_kernel(int64_t n, const float *a, float *out)
+{
+    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * kBlock)
+        out[t] = a[t];
+}
+
+// partial[i][b]: compensated sum of a.b over block b's share of phase i
+__global__ void __launch_bounds__(kBlock) pdot_kernel(int64_t len, const float *a, const float *b,
+                                                      dfloat *partial)
+{
+    const int i = blockIdx.y, blk = blockIdx.x;
+    const float *pa = a + (int64_t)i * len, *pb = b + (int64_t)i * len;
+    dfloat acc{0.f, 0.f};
+    for (int64_t t = (int64_t)blk * kBlock + threadIdx.x; t < len; t += (int64_t)kDotBlocks * kBlock)
+        acc = df_add(acc, dfloat{pa[t] * pb[t], fmaf(pa[t], pb[t], -pa[t] * pb[t])});
+    __shared__ dfloat sh[kBlock];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = kBlock / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off)
+            sh[threadIdx.x] = df_add(sh[threadIdx.x], sh[threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        partial[(int64_t)i * kDotBlocks + blk] = sh[0];
+}
+
+__global__ void pdot_final_kernel(int np, const dfloat *partial, dfloat *out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= np)
+        return;
+    dfloat acc = partial[(int64_t)i * kDotBlocks];
+    for (int b = 1; b < kDotBlocks; ++b)
+        acc = df_add(acc, partial[(int64_t)i * kDotBlocks + b]);
+    out[i] = acc;
+}
+
+__device__ __forceinline__ float ratio(dfloat num, dfloat den)
+{
+    const float d = den.hi + den.lo;
+    return d > 0.f ? (num.hi + num.lo) / d : 0.f;
+}
+
+// x += alpha p (volume), alpha = gamma / qq per phase
+__global__ void __launch_bounds__(kBlock) axpy_vol_kernel(int np, int64_t len, const dfloat *gamma,
+                                                          const dfloat *qq, const float *p, float *x)
+{
+    const int64_t n = (int64_t)np * len;
+    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * kBlock) {
+        const int i = (int)(t / len);
+        x[t] = fmaf(ratio(gamma[i], qq[i]), p[t], x[t]);
+    }
+}
+
+// r -= alpha q (projections)
+__global__ void __launch_bounds__(kBlock) axmy_proj_kernel(int np, int64_t len, const dfloat *gamma,
+                                                           const dfloat *qq, const float *q, float *r)
+{
+    const int64_t n = (int64_t)np * len;
+    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * kBlock) {
+        const int i = (int)(t / len);
+        r[t] = fmaf(-ratio(gamma[i], qq[i]), q[t], r[t]);
+    }
+}
+
+// p = s + beta p, beta = gnew / gamma per phase
+__global__ void __launch_bounds__(kBlock) pupdate_kernel(int np, int64_t len, const dfloat *gnew,
+                                                         const dfloat *gamma, const float *s, float *p)
+{
+    const int64_t n = (int64_t)np * len;
+    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * kBlock) {
+        const int i = (int)(t / len);
+        p[t] = fmaf(ratio(gnew[i], gamma[i]), p[t], s[t]);
+    }
+}
+
+__global__ void scalar_copy_kernel(int np, const dfloat *a, dfloat *b)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < np)
+        b[i] = a[i];
+}
+
+__global__ void __launch_bounds__(kBlock) clamp_kernel(int64_t n, float *x)
+{
+    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * kBlock) {
+        const float v = x[t];
+        x[t] = v < 0.f ? 0.f : v;  // NaN stays NaN
+    }
+}
+
+int64_t grid1(int64_t n)
+{
+    int64_t b = (n + kBlock - 1) / kBlock;
+    return b < 1 ? 1 : (b > 65536 ? 65536 : b);
+}
+
+struct CGWs {
+    float *r, *q, *p, *s;
+    dfloat *gamma, *qq, *gnew, *partial;
+};
+
+CGWs carve(const CTG &g, void *ws)
+{
+    CGWs w;
+    char *c = (char *)ws;
+    const int64_t pr = (int64_t)g.np * g.R, pv = (int64_t)g.np * g.N;
+    w.r = (float *)c;
+    w.q = w.r + pr;
+    w.p = w.q + pr;
+    w.s = w.p + pv;
+    w.gamma = (dfloat *)(w.s + pv);
+    w.qq = w.gamma + g.np;
+    w.gnew = w.qq + g.np;
+    w.partial = w.gnew + g.np;
+    return w;
+}
+
+hipError_t pdot(const CTG &g, int64_t len, const float *a, const float *b, dfloat *partial,
+                dfloat *out, hipStream_t s)
+{
+    pdot_kernel<<<dim3(kDotBlocks, g.np), kBlock, 0, s>>>(len, a, b, partial);
+    pdot_final_kernel<<<(g.np + 63) / 64, 64, 0, s>>>(g.np, partial, out);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+// ---- launchers used by the C ABI ------------------------------------------
+size_t ct_workspace_bytes_impl(int np, int64_t N, int64_t R)
+{
+    return (size_t)np * (2 * R + 2 * N) * sizeof(float) +
+           (size_t)np * (3 + kDotBlocks) * sizeof(dfloat);
+}
+
+static CTG make(const tnlm_ct_geom *p)
+{
+    CTG g;
+    g.np = p->np;
+    g.nx = p->nx;
+    g.ny = p->ny;
+    g.nz = p->nz;
+    g.nu = p->nu;
+    g.nv = p->nv;
+    g.na = p->na;
+    g.sid = p->sid;
+    g.sdd = p->sdd;
+    g.du = p->du;
+    g.dv = p->dv;
+    g.angles = p->angles;
+    g.N = (int64_t)p->nx * p->ny * p->nz;
+    g.R = (int64_t)p->na * p->nu * p->nv;
+    return g;
+}
+
+hipError_t ct_project(const tnlm_ct_geom *p, const float *vol, float *proj, hipStream_t s)
+{
+    const CTG g = make(p);
+    const int64_t n = (int64_t)g.np * g.R;
+    project_kernel<<<(n + kBlock - 1) / kBlock, kBlock, 0, s>>>(g, vol, proj);
+    return hipGetLastError();
+}
+
+hipError_t ct_backproject(const tnlm_ct_geom *p, const float *proj, float *vol, hipStream_t s)
+{
+    const CTG g = make(p);
+    const int64_t n = (int64_t)g.np * g.N;
+    backproject_kernel<<<(n + kBlock - 1) / kBlock, kBlock, 0, s>>>(g, proj, vol);
+    return hipGetLastError();
+}
+
+hipError_t ct_cgls_init(const tnlm_ct_geom *p, const float *y, const float *x, void *ws,
+                        hipStream_t s)
+{
+    const CTG g = make(p);
+    CGWs w = carve(g, ws);
+    const int64_t pr = (int64_t)g.np * g.R, pv = (int64_t)g.np * g.N;
+    hipError_t e = ct_project(p, x, w.q, s);  // q = P x
+    if (e != hipSuccess)
+        return e;
+    sub_kernel<<<grid1(pr), kBlock, 0, s>>>(pr, y, w.q, w.r);  // r = y - P x
+    if ((e = ct_backproject(p, w.r, w.s, s)) != hipSuccess)    // s = P^T r
+        return e;
+    copy_kernel<<<grid1(pv), kBlock, 0, s>>>(pv, w.s, w.p);    // p = s
+    return pdot(g, g.N, w.s, w.s, w.partial, w.gamma, s);      // gamma = |s|^2
+}
+
+hipError_t ct_cgls_step(const tnlm_ct_geom *p, float *x, void *ws, hipStream_t s)
+{
+    const CTG g = make(p);
+    CGWs w = carve(g, ws);
+    const int64_t pr = (int64_t)g.np * g.R, pv = (int64_t)g.np * g.N;
+    hipError_t e = ct_project(p, w.p, w.q, s);  // q = P p
+    if (e != hipSuccess)
+        return e;
+    if ((e = pdot(g, g.R, w.q, w.q, w.partial, w.qq, s)) != hipSuccess)  // qq = |q|^2
+        return e;
+    axpy_vol_kernel<<<grid1(pv), kBlock, 0, s>>>(g.np, g.N, w.gamma, w.qq, w.p, x);
+    axmy_proj_kernel<<<grid1(pr), kBlock, 0, s>>>(g.np, g.R, w.gamma, w.qq, w.q, w.r);
+    if ((e = ct_backproject(p, w.r, w.s, s)) != hipSuccess)  // s = P^T r
+        return e;
+    if ((e = pdot(g, g.N, w.s, w.s, w.partial, w.gnew, s)) != hipSuccess)
+        return e;
+    pupdate_kernel<<<grid1(pv), kBlock, 0, s>>>(g.np, g.N, w.gnew, w.gamma, w.s, w.p);
+    scalar_copy_kernel<<<(g.np + 63) / 64, 64, 0, s>>>(g.np, w.gnew, w.gamma);
+    return hipGetLastError();
+}
+
+hipError_t ct_clamp(float *x, int64_t n, hipStream_t s)
+{
+    clamp_kernel<<<grid1(n), kBlock, 0, s>>>(n, x);
+    return hipGetLastError();
+}
+
+}  // namespace tnlm

@@ -379,4 +379,122 @@ int tnlm_grad(const tnlm_geom *geom, int dtype, const void *u, const void *f, in
     return e == hipSuccess ? TNLM_OK : hip_fail(e);
 }
 
+// ---- reconstruction model ---------------------------------------------------
+static int check_ct(const tnlm_ct_geom *g, int64_t *N, int64_t *R)
+{
+    if (!g)
+        return TNLM_ENULL;
+    if (g->np < 1 || g->nx < 1 || g->ny < 1 || g->nz < 1 || g->nu < 1 || g->nv < 1 || g->na < 1)
+        return TNLM_EINVAL;
+    const float vals[4] = {g->sid, g->sdd, g->du, g->dv};
+    for (float v : vals)
+        if (!(v > 0.f) || !isfinite(v))
+            return TNLM_EINVAL;
+    const double half = 0.5 * sqrt((double)g->nx * g->nx + (double)g->ny * g->ny);
+    if (!(g->sid > half) || !(g->sdd - g->sid > half))
+        return TNLM_EINVAL;
+    *N = (int64_t)g->nx * g->ny * g->nz;
+    *R = (int64_t)g->na * g->nu * g->nv;
+    if (*N * g->np >= (int64_t(1) << 31) || *R * g->np >= (int64_t(1) << 31))
+        return TNLM_ERANGE;
+    if (!g->angles)
+        return TNLM_ENULL;
+    return TNLM_OK;
+}
+
+size_t tnlm_ct_workspace_bytes(const tnlm_ct_geom *geom)
+{
+    int64_t N, R;
+    if (check_ct(geom, &N, &R) != TNLM_OK)
+        return (size_t)-1;
+    return ct_workspace_bytes_impl(geom->np, N, R);
+}
+
+int tnlm_ct_project(const tnlm_ct_geom *geom, const float *vol, float *proj, void *stream)
+{
+    int64_t N, R;
+    int rc = check_ct(geom, &N, &R);
+    if (rc)
+        return rc;
+    if (!vol || !proj)
+        return TNLM_ENULL;
+    if (overlap(vol, (size_t)geom->np * N * 4, proj, (size_t)geom->np * R * 4) ||
+        overlap(geom->angles, (size_t)geom->np * geom->na * 4, proj, (size_t)geom->np * R * 4))
+        return TNLM_EALIAS;
+    hipError_t e = ct_project(geom, vol, proj, (hipStream_t)stream);
+    return e == hipSuccess ? TNLM_OK : hip_fail(e);
+}
+
+int tnlm_ct_backproject(const tnlm_ct_geom *geom, const float *proj, float *vol, void *stream)
+{
+    int64_t N, R;
+    int rc = check_ct(geom, &N, &R);
+    if (rc)
+        return rc;
+    if (!vol || !proj)
+        return TNLM_ENULL;
+    if (overlap(vol, (size_t)geom->np * N * 4, proj, (size_t)geom->np * R * 4) ||
+        overlap(geom->angles, (size_t)geom->np * geom->na * 4, vol, (size_t)geom->np * N * 4))
+        return TNLM_EALIAS;
+    hipError_t e = ct_backproject(geom, proj, vol, (hipStream_t)stream);
+    return e == hipSuccess ? TNLM_OK : hip_fail(e);
+}
+
+int tnlm_cgls_init(const tnlm_ct_geom *geom, const float *y, const float *x, void *ws,
+                   size_t ws_bytes, void *stream)
+{
+    int64_t N, R;
+    int rc = check_ct(geom, &N, &R);
+    if (rc)
+        return rc;
+    if (!y || !x)
+        return TNLM_ENULL;
+    const size_t need = ct_workspace_bytes_impl(geom->np, N, R);
+    if (!ws || ws_bytes < need)
+        return TNLM_EWORKSPACE;
+    const size_t vb = (size_t)geom->np * N * 4, pb = (size_t)geom->np * R * 4;
+    if (overlap(ws, need, y, pb) || overlap(ws, need, x, vb) ||
+        overlap(ws, need, geom->angles, (size_t)geom->np * geom->na * 4))
+        return TNLM_EALIAS;
+    hipError_t e = ct_cgls_init(geom, y, x, ws, (hipStream_t)stream);
+    return e == hipSuccess ? TNLM_OK : hip_fail(e);
+}
+
+int tnlm_cgls_step(const tnlm_ct_geom *geom, float *x, int iters, void *ws, size_t ws_bytes,
+                   void *stream)
+{
+    int64_t N, R;
+    int rc = check_ct(geom, &N, &R);
+    if (rc)
+        return rc;
+    if (iters < 0)
+        return TNLM_EINVAL;
+    if (!x)
+        return TNLM_ENULL;
+    const size_t need = ct_workspace_bytes_impl(geom->np, N, R);
+    if (!ws || ws_bytes < need)
+        return TNLM_EWORKSPACE;
+    if (overlap(ws, need, x, (size_t)geom->np * N * 4) ||
+        overlap(ws, need, geom->angles, (size_t)geom->np * geom->na * 4))
+        return TNLM_EALIAS;
+    for (int k = 0; k < iters; ++k) {
+        hipError_t e = ct_cgls_step(geom, x, ws, (hipStream_t)stream);
+        if (e != hipSuccess)
+            return hip_fail(e);
+    }
+    return TNLM_OK;
+}
+
+int tnlm_clamp_nonneg(float *x, int64_t n, void *stream)
+{
+    if (n < 0)
+        return TNLM_EINVAL;
+    if (n == 0)
+        return TNLM_OK;
+    if (!x)
+        return TNLM_ENULL;
+    hipError_t e = ct_clamp(x, n, (hipStream_t)stream);
+    return e == hipSuccess ? TNLM_OK : hip_fail(e);
+}
+
 }  // extern "C"

@@ -119,4 +119,13 @@ hipError_t launch_grad_exact_generic(const Geo &g, int dtype, const GradArgs &a,
 hipError_t launch_energy_final(const dfloat *partial, int64_t n, float *e_out,
                                hipStream_t s);
 
+// Reconstruction model (ct.hip): projector, transpose, CGLS, positivity.
+size_t ct_workspace_bytes_impl(int np, int64_t N, int64_t R);
+hipError_t ct_project(const tnlm_ct_geom *g, const float *vol, float *proj, hipStream_t s);
+hipError_t ct_backproject(const tnlm_ct_geom *g, const float *proj, float *vol, hipStream_t s);
+hipError_t ct_cgls_init(const tnlm_ct_geom *g, const float *y, const float *x, void *ws,
+                        hipStream_t s);
+hipError_t ct_cgls_step(const tnlm_ct_geom *g, float *x, void *ws, hipStream_t s);
+hipError_t ct_clamp(float *x, int64_t n, hipStream_t s);
+
 }  // namespace tnlm

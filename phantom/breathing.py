@@ -268,6 +268,12 @@ CT_WORKLOADS = {
     # distances in the ratio 100 : 153.6 of the paper's geometry
     "recon64": CTWorkload("recon64", 10, 64, 64, 64, 128, 96, 30, 250.0, 384.0,
                           1.2, 1.2, 6.0, 3.0, 0.0, 1201 + 5),
+    # the paper's scan at 2 mm voxels: 10 phases of 128^3, 300 projections of
+    # 512 x 512 pixels (0.8 mm = 0.4 voxel pitch) over 360 degrees, source at
+    # 100 cm (500 voxels) from the isocentre and 153.6 cm (768) from the
+    # detector
+    "recon128": CTWorkload("recon128", 10, 128, 128, 128, 512, 512, 30, 500.0, 768.0,
+                           0.4, 0.4, 12.0, 6.0, 0.0, 1201 + 6),
 }
 
 

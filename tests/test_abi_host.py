@@ -175,3 +175,42 @@ def test_energy_noalloc_argument_checks():
     big = geom(np_=64, nx=1024, ny=1024, nz=512, M=3)
     assert lib.tnlm_workspace_bytes(ctypes.byref(big), _lib.OP_ENERGY) > (4 << 20)
     assert call(gg=big) == _lib.EWORKSPACE
+
+
+def _ctg(**kw):
+    d = dict(np=2, nx=8, ny=8, nz=8, nu=16, nv=12, na=4, sid=40.0, sdd=64.0, du=1.0,
+             dv=1.0, angles=FAKE3)
+    d.update(kw)
+    return _lib.CTGeom(d["np"], d["nx"], d["ny"], d["nz"], d["nu"], d["nv"], d["na"],
+                       d["sid"], d["sdd"], d["du"], d["dv"], d["angles"])
+
+
+@pytest.mark.parametrize("kw", [dict(np=0), dict(nx=0), dict(nu=0), dict(na=0),
+                                dict(sid=0.0), dict(du=-1.0), dict(dv=float("nan")),
+                                dict(sid=4.0),           # source inside the volume
+                                dict(sdd=42.0)])         # detector inside the volume
+def test_ct_bad_geometry_is_einval(kw):
+    g = _ctg(**kw)
+    assert lib.tnlm_ct_project(ctypes.byref(g), FAKE, FAKE2, None) == _lib.EINVAL
+    assert lib.tnlm_ct_workspace_bytes(ctypes.byref(g)) == ctypes.c_size_t(-1).value
+
+
+def test_ct_argument_checks():
+    g = _ctg()
+    assert lib.tnlm_ct_project(None, FAKE, FAKE2, None) == _lib.ENULL
+    assert lib.tnlm_ct_project(ctypes.byref(g), None, FAKE2, None) == _lib.ENULL
+    assert lib.tnlm_ct_project(ctypes.byref(g), FAKE, FAKE, None) == _lib.EALIAS
+    assert lib.tnlm_ct_backproject(ctypes.byref(g), FAKE, FAKE, None) == _lib.EALIAS
+    assert lib.tnlm_ct_project(ctypes.byref(_ctg(angles=None)), FAKE, FAKE2, None) == _lib.ENULL
+    big = _ctg(np=64, nx=1024, ny=1024, nz=1024, sid=2000.0, sdd=4000.0)
+    assert lib.tnlm_ct_project(ctypes.byref(big), FAKE, FAKE2, None) == _lib.ERANGE
+    need = lib.tnlm_ct_workspace_bytes(ctypes.byref(g))
+    assert need > 0
+    assert lib.tnlm_cgls_init(ctypes.byref(g), FAKE, FAKE2, None, need, None) == _lib.EWORKSPACE
+    assert lib.tnlm_cgls_init(ctypes.byref(g), FAKE, FAKE2, 0x60000000, need - 1,
+                              None) == _lib.EWORKSPACE
+    assert lib.tnlm_cgls_step(ctypes.byref(g), FAKE2, -1, 0x60000000, need, None) == _lib.EINVAL
+    assert lib.tnlm_cgls_step(ctypes.byref(g), FAKE2, 0, 0x60000000, need, None) == _lib.OK
+    assert lib.tnlm_clamp_nonneg(None, 5, None) == _lib.ENULL
+    assert lib.tnlm_clamp_nonneg(FAKE, -1, None) == _lib.EINVAL
+    assert lib.tnlm_clamp_nonneg(None, 0, None) == _lib.OK
