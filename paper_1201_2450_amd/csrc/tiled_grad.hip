@@ -472,7 +472,7 @@ __global__ void __launch_bounds__(256) fold_kernel(Geo g, const float *gpad, flo
 }
 
 // ---------------------------------------------------------------------------
-// Two-stage adjoint for u = f (the gradient of E(f; f)), M <= 4.
+// Two-stage adjoint for u = f (the gradient of E(f; f)), M <= 3.
 //
 // The per-lane blocks above evaluate the distance and Gv on positions grown
 // by a halo around each lane's outputs (4 x 6 Gv positions for 2 x 4
@@ -505,7 +505,11 @@ constexpr int NSEG = 8, THREADS = 32 * NSEG;
 constexpr int NSEG2 = TZ / B2Z;  // segments with stage-2 outputs (15)
 static_assert(GX == 2 * B1X && GZ == (NSEG / 2) * B1Z, "stage-1 blocks tile the Gv field");
 static_assert(NSEG2 <= NSEG && TZ % B2Z == 0, "stage-2 blocks tile the outputs");
-constexpr int kMaxM = 4;
+// up to M = 3 the LDS (u_j, statistics, Gv) stays within 80 KB, so two
+// workgroups share a CU; beyond, one 4-wave workgroup per CU leaves one wave
+// per SIMD and the per-lane kernel is faster (fbs512, M = 4: 3.40 s against
+// 2.22 s)
+constexpr int kMaxM = 3;
 
 template <int M>
 struct Lay {
@@ -525,7 +529,7 @@ struct Lay {
     static_assert((NU + NS + NG) * 4 <= 160 * 1024, "fits the LDS of one CU");
     // up to M = 3 two workgroups share a CU (one computes while the other
     // waits at a barrier)
-    static_assert(M > 3 || (NU + NS + NG) * 4 <= 80 * 1024, "two workgroups per CU");
+    static_assert((NU + NS + NG) * 4 <= 80 * 1024, "two workgroups per CU");
 };
 
 struct Grid {
@@ -866,11 +870,8 @@ void launch_m(const Geo &g, const GradArgs &a, float *gpad, hipStream_t s)
     case 2:
         launch<T, 2>(g, a, gpad, s);
         break;
-    case 3:
-        launch<T, 3>(g, a, gpad, s);
-        break;
     default:
-        launch<T, 4>(g, a, gpad, s);
+        launch<T, 3>(g, a, gpad, s);
         break;
     }
 }
