@@ -8,6 +8,7 @@ outputs max(1e-5, the case's derived rounding-error bound) (tests/gpu_util.py);
 volumes stored in BF16/FP16 additionally half a storage ulp.
 """
 import itertools
+import math
 
 import numpy as np
 import pytest
@@ -355,3 +356,26 @@ def test_enhance_checkpoint_resume_is_bitwise(k_stop):
     resumed = tnlm.enhance(g, mu, d=d, M=M, h=h, iters=7, recompute_every=3, resume=state)
     torch.cuda.synchronize()
     assert torch.equal(resumed, full)
+
+
+@pytest.mark.parametrize("d,M", [(1, 1), (1, 3), (2, 1)])
+def test_nan_in_the_data_reaches_the_same_outputs_as_the_oracle(d, M):
+    """NaN in the volumes is not checked but propagated: one NaN voxel of
+    phase 1 (in u, f and g) makes exactly the oracle's NaN set of the
+    Gauss-Jacobi output NaN (the tiled kernel for d = 1, the generic one for
+    d = 2), every other output matches the oracle, and the energy is NaN."""
+    shape, h, mu = (3, 12, 40, 20), 0.1, 0.5
+    say(f"NaN propagation {shape} d={d} M={M}")
+    u64 = inputs(shape, "phantom", 23)
+    u64[1, 6, 20, 10] = np.nan
+    _, u = to_dev(u64)
+    out = host(tnlm.jacobi_step(u, u, u, mu, d=d, M=M, h=h))
+    ref = oracle.jacobi(u64, u64, u64, mu, d, M, h)
+    assert np.array_equal(np.isnan(out), np.isnan(ref))
+    ok = ~np.isnan(ref)
+    assert np.isfinite(out[ok]).all()
+    err = np.max(np.abs(out[ok] - ref[ok])) / np.max(np.abs(ref[ok]))
+    assert err <= 1e-5, err
+    e, _ = tnlm.energy(u, d=d, M=M, h=h)
+    torch.cuda.synchronize()
+    assert math.isnan(float(e[0]) + float(e[1]))

@@ -413,3 +413,21 @@ def test_oracle_on_phantom_is_finite_and_normalised():
     w, lse = oracle.weights(u, 1, 2, 0.05)
     assert np.isfinite(w).all() and np.isfinite(lse).all()
     assert np.abs(w.sum(axis=2) - 1).max() <= 1e-13
+
+
+def test_nan_in_the_data_reaches_exactly_the_outputs_that_read_it():
+    """NaN in the volumes is not checked; it propagates. One NaN voxel at
+    c of phase 1 (in u, f and g) reaches, in one Eq.-(8) step, the outputs
+    of phases 0 and 2 whose windows of candidate patches touch it
+    (Chebyshev distance <= M + d) and the outputs of phase 1 whose own patch
+    or fidelity term touches it (<= d); every other output stays finite,
+    and the energy, which sums all terms, is NaN."""
+    d, M = 1, 1
+    u = np.random.default_rng(5).random((3, 8, 8, 8))
+    u[1, 4, 4, 4] = np.nan
+    out = oracle.jacobi(u, u, u, 0.5, d, M, 0.1)
+    cheb = np.max(np.abs(np.indices((8, 8, 8)) - 4), axis=0)
+    for i, reach in ((0, M + d), (1, d), (2, M + d)):
+        assert np.array_equal(np.isnan(out[i]), cheb <= reach), i
+        assert np.isfinite(out[i][cheb > reach]).all()
+    assert np.isnan(oracle.energy(u, u, d, M, 0.1))
