@@ -25,6 +25,7 @@ namespace tnlm {
 namespace {
 
 constexpr int kBlock = 256;
+constexpr float kFootMargin = 1e-2f;  // pixels added around a voxel's footprint
 
 struct CTG {
     int np, nx, ny, nz, nu, nv, na;
@@ -95,43 +96,51 @@ __global__ void __launch_bounds__(kBlock) project_kernel(CTG g, const float *vol
     const float L = sqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
     // voxel of the entry point, clamped to the grid (on the entry face the
     // coordinate is at the box boundary; where it lies on a plane between two
-    // voxels either is right: the walk then takes a zero-length step)
-    int idx[3], step[3];
-    float inv[3];
+    // voxels either is right: the walk then takes a zero-length step).
+    // Per axis the walk keeps the coordinate of the next plane it will cross
+    // (an exact half-integer); the crossing parameter is recomputed from it
+    // every step, so errors do not accumulate. An axis the ray runs parallel
+    // to gets plane +inf and slope 1, i.e. crossing parameter +inf.
+    float pl[3], inv[3], pstep[3];
+    int off = 0, ostep[3];
+    const int stride[3] = {g.ny * g.nz, g.nz, 1};
     for (int k = 0; k < 3; ++k) {
         const float p = S[k] + tin * d[k] + c[k] + 0.5f;
-        int q = (int)floorf(p);
-        idx[k] = q < 0 ? 0 : (q > n[k] - 1 ? n[k] - 1 : q);
-        step[k] = d[k] > 0.f ? 1 : (d[k] < 0.f ? -1 : 0);
-        inv[k] = d[k] != 0.f ? 1.f / d[k] : 0.f;
+        const int q = (int)floorf(p);
+        const int ik = q < 0 ? 0 : (q > n[k] - 1 ? n[k] - 1 : q);
+        off += ik * stride[k];
+        const int sk = d[k] > 0.f ? 1 : (d[k] < 0.f ? -1 : 0);
+        pl[k] = sk == 0 ? INFINITY : (float)(ik + (sk > 0 ? 1 : 0)) - 0.5f - c[k];
+        inv[k] = sk == 0 ? 1.f : 1.f / d[k];
+        pstep[k] = (float)sk;
+        ostep[k] = sk * stride[k];
     }
     const float *v = vol + (int64_t)i * g.N;
+    const unsigned nvox = (unsigned)g.N;
     float acc = 0.f, tc = tin;
     const int maxsteps = g.nx + g.ny + g.nz + 3;
     for (int it = 0; it < maxsteps; ++it) {
-        // next plane crossing along each axis, from the plane index
-        float tn[3];
-        for (int k = 0; k < 3; ++k) {
-            if (step[k] == 0) {
-                tn[k] = INFINITY;
-            } else {
-                const float plane = (float)(idx[k] + (step[k] > 0 ? 1 : 0)) - 0.5f - c[k];
-                tn[k] = (plane - S[k]) * inv[k];
-            }
-        }
-        int ax = 0;
-        if (tn[1] < tn[ax])
-            ax = 1;
-        if (tn[2] < tn[ax])
-            ax = 2;
-        const float te = fminf(tn[ax], tout);
-        if (te > tc)
-            acc = fmaf((te - tc) * L, v[((int64_t)idx[0] * g.ny + idx[1]) * g.nz + idx[2]], acc);
+        const float t0 = (pl[0] - S[0]) * inv[0];
+        const float t1 = (pl[1] - S[1]) * inv[1];
+        const float t2 = (pl[2] - S[2]) * inv[2];
+        const float tm = fminf(fminf(t0, t1), t2);
+        const float te = fminf(tm, tout);
+        const float nacc = fmaf((te - tc) * L, v[off], acc);
+        acc = te > tc ? nacc : acc;
         if (te >= tout)
             break;
         tc = te;
-        idx[ax] += step[ax];
-        if (idx[ax] < 0 || idx[ax] >= n[ax])
+        // step every axis whose crossing is the nearest (a tie is a ray
+        // through an edge or corner: the voxels skipped have zero length)
+        const bool h0 = t0 == tm, h1 = t1 == tm, h2 = t2 == tm;
+        pl[0] += h0 ? pstep[0] : 0.f;
+        pl[1] += h1 ? pstep[1] : 0.f;
+        pl[2] += h2 ? pstep[2] : 0.f;
+        off += (h0 ? ostep[0] : 0) + (h1 ? ostep[1] : 0) + (h2 ? ostep[2] : 0);
+        // the exit face ends the walk through te >= tout (its crossing is
+        // computed exactly as the box's exit parameter); this guard only
+        // keeps the reads inside the phase
+        if ((unsigned)off >= nvox)
             break;
     }
     proj[t] = acc;
@@ -147,28 +156,36 @@ __global__ void __launch_bounds__(kBlock) backproject_kernel(CTG g, const float 
     const int z = (int)(vv % g.nz), y = (int)((vv / g.nz) % g.ny), x = (int)(vv / ((int64_t)g.nz * g.ny));
     const float cen[3] = {x - 0.5f * (g.nx - 1), y - 0.5f * (g.ny - 1), z - 0.5f * (g.nz - 1)};
     const float ucen = 0.5f * (g.nu - 1), vcen = 0.5f * (g.nv - 1);
+    const float rdu = 1.f / g.du, rdv = 1.f / g.dv;
     float acc = 0.f;
     for (int a = 0; a < g.na; ++a) {
         const float th = g.angles[(int64_t)i * g.na + a];
         float s, c;
         sincosf(th, &s, &c);
-        // footprint: the corners projected onto the detector (pixel units)
-        float umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY;
-        for (int k = 0; k < 8; ++k) {
+        // footprint: bounding box of the corners projected onto the detector
+        // (pixel units). The detector coordinate u and the magnification m
+        // depend on a corner's (X, Y) only, v on Z times m (m > 0: the depth
+        // w stays above zero, the source lies outside the volume). The box
+        // only selects candidate pixels, each of which is clipped exactly
+        // below, so it is built with approximate reciprocals and widened by
+        // kFootMargin pixels, far more than their rounding.
+        float umin = INFINITY, umax = -INFINITY, mmin = INFINITY, mmax = -INFINITY;
+        for (int k = 0; k < 4; ++k) {
             const float X = cen[0] + ((k & 1) ? 0.5f : -0.5f);
             const float Y = cen[1] + ((k & 2) ? 0.5f : -0.5f);
-            const float Z = cen[2] + ((k & 4) ? 0.5f : -0.5f);
-            const float w = g.sid - (X * c + Y * s);  // depth from the source
-            const float m = g.sdd / w;
-            const float u = (-X * s + Y * c) * m / g.du + ucen;
-            const float vz = Z * m / g.dv + vcen;
+            const float m = g.sdd * __builtin_amdgcn_rcpf(g.sid - (X * c + Y * s));
+            const float u = (-X * s + Y * c) * m;
             umin = fminf(umin, u);
             umax = fmaxf(umax, u);
-            vmin = fminf(vmin, vz);
-            vmax = fmaxf(vmax, vz);
+            mmin = fminf(mmin, m);
+            mmax = fmaxf(mmax, m);
         }
-        // clamped in float before converting (the depth w stays above zero:
-        // the source lies outside the volume)
+        const float zlo = cen[2] - 0.5f, zhi = cen[2] + 0.5f;
+        const float vmin = zlo * (zlo < 0.f ? mmax : mmin) * rdv + vcen - kFootMargin;
+        const float vmax = zhi * (zhi < 0.f ? mmin : mmax) * rdv + vcen + kFootMargin;
+        umin = umin * rdu + ucen - kFootMargin;
+        umax = umax * rdu + ucen + kFootMargin;
+        // clamped in float before converting
         const int u0 = (int)fmaxf(0.f, ceilf(umin)), u1 = (int)fminf(g.nu - 1.f, floorf(umax));
         const int v0 = (int)fmaxf(0.f, ceilf(vmin)), v1 = (int)fminf(g.nv - 1.f, floorf(vmax));
         const float *pa = proj + ((int64_t)i * g.na + a) * g.nu * g.nv;
