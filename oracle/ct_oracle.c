@@ -27,6 +27,12 @@
  * voxel v (entry and exit parameters along each axis): for each x-slab the
  * ray crosses, the voxels of that slab its y and z ranges touch are
  * candidates, and each candidate's length is computed from its own cube.
+ *
+ * A ray parallel to an axis and lying exactly in a plane between two voxel
+ * layers touches both closed cubes; it is counted in one of them, so that
+ * the lengths of every ray partition its chord through the volume: along
+ * such an axis a voxel's cube is taken half-open, [lo, hi), except that the
+ * last voxel keeps its outer face (the grid's own box is closed).
  */
 #include <math.h>
 #include <stdint.h>
@@ -77,6 +83,11 @@ static int axis_interval(const ray3 *r, int k, double lo, double hi, double *t0,
 static double voxel_length(const ctgeom *g, const ray3 *r, int64_t ix, int64_t iy, int64_t iz)
 {
     const double cen[3] = {ix - 0.5 * (g->nx - 1), iy - 0.5 * (g->ny - 1), iz - 0.5 * (g->nz - 1)};
+    const int64_t idx[3] = {ix, iy, iz}, n[3] = {g->nx, g->ny, g->nz};
+    /* a ray in the face plane between two voxels belongs to the upper one */
+    for (int k = 0; k < 3; ++k)
+        if (r->d[k] == 0.0 && r->S[k] == cen[k] + 0.5 && idx[k] < n[k] - 1)
+            return 0.0;
     double tin = -INFINITY, tout = INFINITY;
     for (int k = 0; k < 3; ++k) {
         double a, b;

@@ -4,6 +4,8 @@
     computed independently from the geometry's definition (slab clipping in
     phantom.box_projections): pins the source side, the detector axes, the
     angle sense, the candidate enumeration and every length;
+  * rays lying in a plane between two voxel layers are counted once: their
+    lengths add up to the chord, like every other ray's;
   * <P x, y> = <x, P^T y> for random x, y: pins the transpose's indexing;
   * the voxelised breathing phantom's projections approach the analytic line
     integrals of its ellipsoids as the voxels shrink (first order);
@@ -46,6 +48,27 @@ def test_voxel_aligned_box_projects_to_its_chords(shape):
     got = ct.project(g, ang, vol)
     assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
     assert (want > 0).sum() > 100  # the box is seen by many rays
+
+
+def test_rays_in_voxel_face_planes_are_counted_once():
+    """Rays parallel to an axis that run exactly in a plane between two
+    voxel layers (the centre detector row of an even-nz grid lies in z = 0;
+    at angle 0 the centre column of an even-ny grid lies in y = 0): the
+    lengths of such a ray, like those of every other ray, add up to its
+    chord through the volume, so a uniform volume projects to the chord
+    lengths of the volume's box (a ray in a face plane is counted in one of
+    the two voxel layers, not in both)."""
+    nx, ny, nz, nu, nv = 8, 6, 4, 9, 7
+    w = CTWorkload("t", 1, nx, ny, nz, nu, nv, 3, 30.0, 50.0, 1.5, 1.5, 1.0, 1.0, 0.0, 7)
+    g = ct.CTGeom(1, nx, ny, nz, nu, nv, 3, w.sid, w.sdd, w.du, w.dv)
+    ang = np.array([[0.0, 1.0, 2.5]])
+    c = np.array([(nx - 1) / 2, (ny - 1) / 2, (nz - 1) / 2])
+    want = box_projections(w, ang, -c - 0.5, c + 0.5, 1.0)
+    got = ct.project(g, ang, np.ones(g.vol_shape))
+    assert np.abs(got - want).max() <= 1e-12 * np.abs(want).max()
+    # the degenerate rays are there: the centre row of every angle, the
+    # centre column at angle 0
+    assert (want[0, :, :, nv // 2] > 0).sum() >= 15 and want[0, 0, nu // 2, nv // 2] > 0
 
 
 def test_transpose_is_the_adjoint():
