@@ -40,6 +40,12 @@ PEAK_FP32_NONPACKED_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 
 # direction: exponent 2, numerator FMA 2, normaliser add 1 (x2 directions)
 FLOP_PER_UPDATE_PER_OFFSET = 18
 FLOP_PER_VOXEL_OFFSET_ADJOINT = 35
+# algorithmic flops per (ray, voxel) pair of the cone-beam projector and of
+# its transpose (the same pairs): the stepped axis's next crossing (one
+# multiply-add, 2), the least of the three crossings (2 comparisons), the
+# length inside the voxel (difference times the ray's length scale, 2) and
+# the accumulation (one fused multiply-add, 2)
+FLOP_PER_RAY_VOXEL = 8
 
 
 def log(*a):
@@ -213,6 +219,81 @@ def regulariser(args, w, dev):
         "breakdown_ms": ms, "roofline": roofline, "cpu_baseline": cpu}), flush=True)
 
 
+def recon_cpu_sample(name, target_s, cg_iters=10):
+    """The FP64 oracle on a bounded sample of the reconstruction workload:
+    the projector and its transpose for a few of phase 0's angles (every
+    detector pixel; the angles spread over the circle) and one Gauss-Jacobi
+    step at random voxels, each scaled to the whole workload and combined as
+    one TNLM-R outer iteration ((cg_iters + 1) projector/transpose pairs plus
+    the Eq. (8) step). Also returns the mean number of voxels a ray crosses
+    (positive lengths), from the same projector sample."""
+    import numpy as np
+
+    from oracle import ct as OCT
+    from oracle import oracle
+    from phantom.breathing import CT_WORKLOADS, ct_angles
+
+    w = CT_WORKLOADS[name]
+    ang = ct_angles(w.np_, w.na)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    rng = np.random.default_rng(9)
+    vol = rng.random((1, w.nx, w.ny, w.nz))
+
+    def geom(k):
+        return OCT.CTGeom(1, w.nx, w.ny, w.nz, w.nu, w.nv, k, w.sid, w.sdd, w.du, w.dv)
+
+    # projector: angles 0, s, 2s, ... of phase 0 until a third of the budget
+    order = list(range(0, w.na, max(1, w.na // 6))) + list(range(w.na))
+    seen, cnt_sum, rays, tp = [], 0.0, 0, 0.0
+    for a in order:
+        if a in seen:
+            continue
+        seen.append(a)
+        sel = np.array([[ang[0, a]]])
+        t0 = time.perf_counter()
+        _, cnt, _ = OCT.project(geom(1), sel, vol, want_stats=True)
+        tp += time.perf_counter() - t0
+        cnt_sum += float(cnt.sum())
+        rays += cnt.size
+        if tp >= target_s / 3 or len(seen) == w.na:
+            break
+    n_p = len(seen)
+    # transpose: the same angles, one at a time, until another third
+    tb, n_b = 0.0, 0
+    for a in seen:
+        sel = np.array([[ang[0, a]]])
+        yv = rng.random((1, 1, w.nu, w.nv))
+        t0 = time.perf_counter()
+        OCT.backproject(geom(1), sel, yv)
+        tb += time.perf_counter() - t0
+        n_b += 1
+        if tb >= target_s / 3:
+            break
+    # Eq. (8) step (window 5^3, patch 3^3) at random voxels
+    x = rng.random((w.np_, w.nx, w.ny, w.nz))
+    tj, n_j, n = 0.0, 0, 4096
+    while tj < target_s / 3:
+        idx = rng.choice(x.size, size=n, replace=False)
+        t0 = time.perf_counter()
+        oracle.jacobi(x, x, x, 0.5, 1, 2, 0.05, idx=idx)
+        tj += time.perf_counter() - t0
+        n_j += n
+        n = int(min(x.size, max(4096, n_j / tj * min(max(target_s / 3 - tj, 0.0), 5.0))))
+    total_angles = w.np_ * w.na
+    p_full = tp / n_p * total_angles
+    b_full = tb / n_b * total_angles
+    j_full = tj / n_j * x.size
+    outer_s = (cg_iters + 1) * (p_full + b_full) + j_full
+    return {"value": outer_s * 1e3, "unit": "ms", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(),
+            "sample": f"FP64 oracle on {n_p} (projector) and {n_b} (transpose) of "
+                      f"{total_angles} projections of the {name} workload (all "
+                      f"{w.nu}x{w.nv} pixels each) and one Eq. (8) step at {n_j} random "
+                      f"voxels, {tp + tb + tj:.1f} s on {threads} OpenMP threads, scaled to "
+                      f"one TNLM-R outer iteration ({cg_iters + 1} projector/transpose "
+                      f"pairs + the Eq. (8) step)"}, cnt_sum / rays
+
+
 def reconstruction(name, dev, cg_iters=10, reps=2):
     """One outer iteration of the TNLM-R algorithm on a cone-beam workload:
     cg_iters CGLS iterations of (P1) for all phases, one Gauss-Jacobi step
@@ -258,6 +339,37 @@ def reconstruction(name, dev, cg_iters=10, reps=2):
             "rays_per_s_project": w.np_ * w.na * w.nu * w.nv / (proj_ms / 1e3)}
 
 
+def recon_main(args, dev):
+    """Prints the JSON line of the reconstruction workload: one TNLM-R outer
+    iteration, with the roofline of its dominant kernel (the transpose of the
+    projector) and the oracle's time on a bounded sample."""
+    r = reconstruction(args.workload, dev)
+    cpu, pairs_per_ray = None, None
+    if not args.no_cpu_baseline:
+        log("timing the FP64 oracle on a sample ...")
+        cpu, pairs_per_ray = recon_cpu_sample(args.workload, args.cpu_seconds)
+    roof = None
+    if pairs_per_ray is not None:
+        rays = r["phases"] * r["angles_per_phase"] * r["detector"][0] * r["detector"][1]
+        flop = rays * pairs_per_ray * FLOP_PER_RAY_VOXEL
+        ach = flop / (r["backproject_ms"] / 1e3) / 1e12
+        roof = {"bound": "alu", "achieved": ach, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": ach / PEAK_FP32_TFLOPS, "traffic": None,
+                "kernel": "tnlm_ct_backproject",
+                "algorithmic_flop_per_launch": flop,
+                "ray_voxel_pairs_per_launch": rays * pairs_per_ray,
+                "peak_without_packed_fp32": PEAK_FP32_NONPACKED_TFLOPS,
+                "frac_without_packed_fp32": ach / PEAK_FP32_NONPACKED_TFLOPS,
+                "projector_achieved": flop / (r["project_ms"] / 1e3) / 1e12}
+        r["ray_voxel_pairs_per_ray"] = pairs_per_ray
+    print(json.dumps({"metric": "TNLM-R outer iteration ms (CGLS + Eq. 8 + positivity)",
+                      "value": r["tnlm_r_outer_iteration_ms"], "unit": "ms",
+                      "higher_is_better": False, "n_gpus": 1, "dtype": "f32",
+                      "data": "synthetic", "config": {"workload": args.workload},
+                      "breakdown": r, "roofline": roof, "cpu_baseline": cpu,
+                      "vs_baseline": None}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -283,15 +395,8 @@ def main():
 
     dev = torch.device("cuda", 0)
     if args.workload.startswith("recon"):
-        # the reconstruction model alone (not the default): timings only
-        r = reconstruction(args.workload, dev)
-        print(json.dumps({"metric": "TNLM-R outer iteration ms (CGLS + Eq. 8 + positivity)",
-                          "value": r["tnlm_r_outer_iteration_ms"], "unit": "ms",
-                          "higher_is_better": False, "n_gpus": 1, "dtype": "f32",
-                          "data": "synthetic", "config": {"workload": args.workload},
-                          "breakdown": r, "roofline": None, "cpu_baseline": None,
-                          "vs_baseline": None}), flush=True)
-        return
+        # the reconstruction model alone (not the default)
+        return recon_main(args, dev)
     w = WORKLOADS[args.workload]
     if w.mu is None:
         return regulariser(args, w, dev)

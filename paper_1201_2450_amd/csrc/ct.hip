@@ -11,7 +11,10 @@
 // centre falls in that footprint has its ray clipped against the voxel's
 // cube; length x projection value is summed. Both enumerate the same
 // (ray, voxel) pairs with the same lengths (up to rounding), in gather form:
-// no atomics, deterministic.
+// no atomics, deterministic. A ray parallel to an axis that runs exactly in
+// the face plane between two voxel layers is counted in the upper layer only
+// (the walk's floor of the entry coordinate; half-open cubes in the
+// transpose), so the lengths of every ray add up to its chord.
 //
 // Geometry (voxel units): for gantry angle t the source is at
 // sid (cos t, sin t, 0); pixel (iu, iv) is centred at
@@ -62,6 +65,17 @@ __device__ __forceinline__ bool slab(float S, float d, float lo, float hi, float
     t0 = fminf(a, b);
     t1 = fmaxf(a, b);
     return true;
+}
+
+// slab() for one voxel's cube in the transpose: a ray parallel to the axis
+// that lies in the face plane between two voxels belongs to the upper one
+// (the cube is half-open, [lo, hi), except for the last voxel along the
+// axis), as the projector's walk assigns it
+__device__ __forceinline__ bool vslab(float S, float d, float lo, float hi, bool last, float &t0,
+                                      float &t1)
+{
+    const bool in = slab(S, d, lo, hi, t0, t1);
+    return in && (d != 0.f || S < hi || last);
 }
 
 __global__ void __launch_bounds__(kBlock) project_kernel(CTG g, const float *vol, float *proj)
@@ -146,22 +160,65 @@ __global__ void __launch_bounds__(kBlock) project_kernel(CTG g, const float *vol
     proj[t] = acc;
 }
 
+// The transpose reads two per-block tables from LDS when they fit
+// (kTabBytes): the sine and cosine of every angle of the phases the block's
+// voxels belong to, and for every detector row iv the reciprocal of the
+// ray's axial component (iv - (nv-1)/2) dv, which sets the z slab of every
+// pixel's clipping. Both hold the values the threads would compute
+// themselves, so the results do not depend on whether they are used.
+constexpr int kTabBytes = 32 * 1024;
+
+// phases a block of kBlock consecutive voxels can touch
+__host__ __device__ inline int block_phase_span(const CTG &g)
+{
+    const int64_t s = (kBlock - 1) / g.N + 2;
+    return (int)(s < g.np ? s : g.np);
+}
+
+template <bool TAB>
 __global__ void __launch_bounds__(kBlock) backproject_kernel(CTG g, const float *proj, float *vol)
 {
-    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    extern __shared__ float tab[];  // [span][na] (sin, cos) pairs, then [nv]
+    const int64_t tb = (int64_t)blockIdx.x * kBlock;
+    const int ib = (int)(tb / g.N);  // first phase of the block
+    const int nang = TAB ? block_phase_span(g) * g.na : 0;
+    const float vcen = 0.5f * (g.nv - 1);
+    if (TAB) {
+        for (int k = threadIdx.x; k < nang; k += kBlock) {
+            const int ph = ib + k / g.na;
+            float sn = 0.f, cs = 1.f;
+            if (ph < g.np)
+                sincosf(g.angles[(int64_t)ph * g.na + k % g.na], &sn, &cs);
+            tab[2 * k] = sn;
+            tab[2 * k + 1] = cs;
+        }
+        for (int k = threadIdx.x; k < g.nv; k += kBlock)
+            tab[2 * nang + k] = 1.f / ((k - vcen) * g.dv);  // +-inf on a centre row
+        __syncthreads();
+    }
+    const int64_t t = tb + threadIdx.x;
     if (t >= (int64_t)g.np * g.N)
         return;
     const int i = (int)(t / g.N);
     const int64_t vv = t - (int64_t)i * g.N;
     const int z = (int)(vv % g.nz), y = (int)((vv / g.nz) % g.ny), x = (int)(vv / ((int64_t)g.nz * g.ny));
     const float cen[3] = {x - 0.5f * (g.nx - 1), y - 0.5f * (g.ny - 1), z - 0.5f * (g.nz - 1)};
-    const float ucen = 0.5f * (g.nu - 1), vcen = 0.5f * (g.nv - 1);
+    const float ucen = 0.5f * (g.nu - 1);
     const float rdu = 1.f / g.du, rdv = 1.f / g.dv;
+    const float zlo = cen[2] - 0.5f, zhi = cen[2] + 0.5f;
+    // a ray with no axial component (z = 0): inside the half-open cube
+    const bool zin0 = zlo <= 0.f && (zhi > 0.f || (zhi == 0.f && z == g.nz - 1));
     float acc = 0.f;
     for (int a = 0; a < g.na; ++a) {
         const float th = g.angles[(int64_t)i * g.na + a];
         float s, c;
-        sincosf(th, &s, &c);
+        if (TAB) {
+            const int k = (i - ib) * g.na + a;
+            s = tab[2 * k];
+            c = tab[2 * k + 1];
+        } else {
+            sincosf(th, &s, &c);
+        }
         // footprint: bounding box of the corners projected onto the detector
         // (pixel units). The detector coordinate u and the magnification m
         // depend on a corner's (X, Y) only, v on Z times m (m > 0: the depth
@@ -180,7 +237,6 @@ __global__ void __launch_bounds__(kBlock) backproject_kernel(CTG g, const float 
             mmin = fminf(mmin, m);
             mmax = fmaxf(mmax, m);
         }
-        const float zlo = cen[2] - 0.5f, zhi = cen[2] + 0.5f;
         const float vmin = zlo * (zlo < 0.f ? mmax : mmin) * rdv + vcen - kFootMargin;
         const float vmax = zhi * (zhi < 0.f ? mmin : mmax) * rdv + vcen + kFootMargin;
         umin = umin * rdu + ucen - kFootMargin;
@@ -189,24 +245,39 @@ __global__ void __launch_bounds__(kBlock) backproject_kernel(CTG g, const float 
         const int u0 = (int)fmaxf(0.f, ceilf(umin)), u1 = (int)fminf(g.nu - 1.f, floorf(umax));
         const int v0 = (int)fmaxf(0.f, ceilf(vmin)), v1 = (int)fminf(g.nv - 1.f, floorf(vmax));
         const float *pa = proj + ((int64_t)i * g.na + a) * g.nu * g.nv;
-        for (int iu = u0; iu <= u1; ++iu)
+        for (int iu = u0; iu <= u1; ++iu) {
+            // the ray of pixel (iu, iv): source S = sid (c, s, 0), direction
+            // d = (dxy, ov) with dxy from iu alone and ov from iv alone
+            const float ou = (iu - ucen) * g.du;
+            const float S0 = g.sid * c, S1 = g.sid * s;
+            const float d0 = -g.sdd * c - ou * s, d1 = -g.sdd * s + ou * c;
+            float txy0, txy1, a0, a1;
+            bool hxy = vslab(S0, d0, cen[0] - 0.5f, cen[0] + 0.5f, x == g.nx - 1, a0, a1);
+            txy0 = fmaxf(-INFINITY, a0);
+            txy1 = fminf(INFINITY, a1);
+            hxy = vslab(S1, d1, cen[1] - 0.5f, cen[1] + 0.5f, y == g.ny - 1, a0, a1) && hxy;
+            txy0 = fmaxf(txy0, a0);
+            txy1 = fminf(txy1, a1);
             for (int iv = v0; iv <= v1; ++iv) {
-                float S[3], d[3];
-                ray_of(g, th, iu, iv, S, d);
-                float tin = -INFINITY, tout = INFINITY;
-                bool hit = true;
-                for (int k = 0; k < 3; ++k) {
-                    float a0, a1;
-                    const bool in = slab(S[k], d[k], cen[k] - 0.5f, cen[k] + 0.5f, a0, a1);
-                    hit = hit && in;
-                    tin = fmaxf(tin, a0);
-                    tout = fminf(tout, a1);
+                const float ov = (iv - vcen) * g.dv;
+                float z0, z1;
+                bool zin;
+                if (TAB) {
+                    const float inv = tab[2 * nang + iv];
+                    const float za = zlo * inv, zb = zhi * inv;
+                    z0 = ov == 0.f ? -INFINITY : fminf(za, zb);
+                    z1 = ov == 0.f ? INFINITY : fmaxf(za, zb);
+                    zin = ov != 0.f || zin0;
+                } else {
+                    zin = vslab(0.f, ov, zlo, zhi, z == g.nz - 1, z0, z1);
                 }
-                if (hit && tout > tin) {
-                    const float L = sqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+                const float tin = fmaxf(txy0, z0), tout = fminf(txy1, z1);
+                if (hxy && zin && tout > tin) {
+                    const float L = sqrtf(d0 * d0 + d1 * d1 + ov * ov);
                     acc = fmaf((tout - tin) * L, pa[(int64_t)iu * g.nv + iv], acc);
                 }
             }
+        }
     }
     vol[t] = acc;
 }
@@ -398,7 +469,12 @@ hipError_t ct_backproject(const tnlm_ct_geom *p, const float *proj, float *vol, 
 {
     const CTG g = make(p);
     const int64_t n = (int64_t)g.np * g.N;
-    backproject_kernel<<<(n + kBlock - 1) / kBlock, kBlock, 0, s>>>(g, proj, vol);
+    const int64_t grid = (n + kBlock - 1) / kBlock;
+    const int64_t tab = ((int64_t)block_phase_span(g) * g.na * 2 + g.nv) * sizeof(float);
+    if (tab <= kTabBytes)
+        backproject_kernel<true><<<grid, kBlock, (size_t)tab, s>>>(g, proj, vol);
+    else
+        backproject_kernel<false><<<grid, kBlock, 0, s>>>(g, proj, vol);
     return hipGetLastError();
 }
 

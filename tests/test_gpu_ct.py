@@ -53,6 +53,13 @@ GEOMS = [
     (16, 16, 16, 32, 24, 6, 2, 60.0, 96.0, 1.1, 1.1),
     (13, 17, 9, 27, 19, 5, 3, 50.0, 80.0, 1.3, 0.9),   # odd, ragged, anisotropic pixels
     (24, 20, 12, 40, 20, 4, 1, 90.0, 140.0, 1.0, 1.2),
+    # 2 x 2100 angles: the transpose's per-block angle table no longer fits
+    # its LDS budget, so it takes its sines and cosines from sincosf
+    (6, 5, 4, 8, 7, 2100, 2, 30.0, 50.0, 1.5, 1.5),
+    # even ny and nz, odd nu and nv: the centre row's rays run in the plane
+    # z = 0 between two voxel layers, and at angle 0 the centre column's in
+    # y = 0 (each counted in one layer)
+    (8, 6, 4, 9, 7, 5, 2, 30.0, 50.0, 1.5, 1.5),
 ]
 
 
