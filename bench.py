@@ -488,6 +488,10 @@ def main():
         roofline["counter_frac"] = c / PEAK_FP32_TFLOPS
         roofline["counter_flop_per_launch"] = prof["counter_flop"]
         roofline["counter_frac_without_packed_fp32"] = c / PEAK_FP32_NONPACKED_TFLOPS
+        roofline["counter_note"] = ("hardware FP32 operation count: includes work the "
+                                    "algorithmic count leaves out (each distance once per "
+                                    "direction, lane-block halos, reference distances); "
+                                    "frac is the algorithmic figure")
 
     def time_ms(fn, reps=2):
         fn()

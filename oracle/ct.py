@@ -73,6 +73,11 @@ def _L():
         g = ctypes.POINTER(_G)
         lib.ctor_project.argtypes = [g, dp, dp, dp, dp, dp]
         lib.ctor_backproject.argtypes = [g, dp, dp, dp, dp, dp]
+        lib.ctor_error_model.argtypes = [g, dp, dp, dp, dp, dp]
+        i64 = ctypes.c_int64
+        lib.ctor_pair_error.argtypes = [g, ctypes.c_double, i64, i64, i64, i64, i64,
+                                        ctypes.POINTER(ctypes.c_double)]
+        lib.ctor_pair_error.restype = ctypes.c_double
         lib.ctor_box_chord.argtypes = [g, ctypes.c_double, ctypes.c_int64,
                                        ctypes.c_int64, dp, dp]
         lib.ctor_box_chord.restype = ctypes.c_double
@@ -120,6 +125,30 @@ def backproject(geo: CTGeom, angles, proj, want_stats=False):
     _L().ctor_backproject(ctypes.byref(_g(geo)), _dp(angles), _dp(proj),
                           _dp(out), _dp(cnt), _dp(sab))
     return (out, cnt, sab) if want_stats else out
+
+
+def error_model(geo: CTGeom, angles, xabs=None, yabs=None):
+    """First-order rounding-error bounds of an FP32 evaluation of P and P^T
+    (see ct_oracle.c): per ray for P applied to a volume of magnitudes xabs,
+    per voxel for P^T applied to projections of magnitudes yabs. Returns
+    (eproj or None, evol or None)."""
+    angles = _c(angles)
+    assert angles.shape == (geo.np_, geo.na)
+    xa = _c(xabs) if xabs is not None else None
+    ya = _c(yabs) if yabs is not None else None
+    ep = np.empty(geo.proj_shape) if xa is not None else None
+    ev = np.empty(geo.vol_shape) if ya is not None else None
+    _L().ctor_error_model(ctypes.byref(_g(geo)), _dp(angles), _dp(xa), _dp(ya), _dp(ep), _dp(ev))
+    return ep, ev
+
+
+def pair_error(geo: CTGeom, theta, iu, iv, voxel):
+    """(exact length of ray (theta, iu, iv) in voxel (ix, iy, iz), its FP32
+    error bound under error_model's model)."""
+    ln = ctypes.c_double()
+    b = _L().ctor_pair_error(ctypes.byref(_g(geo)), float(theta), int(iu), int(iv),
+                             *[int(k) for k in voxel], ctypes.byref(ln))
+    return ln.value, b
 
 
 def box_chord(geo: CTGeom, theta, iu, iv, lo, hi):

@@ -46,6 +46,7 @@ typedef struct {
 
 typedef struct {
     double S[3], d[3]; /* ray: X(t) = S + t d, t in [0, 1] reaches the pixel */
+    double c, s, ou;   /* cos, sin of the angle; lateral pixel offset */
 } ray3;
 
 static ray3 make_ray(const ctgeom *g, double th, int64_t iu, int64_t iv)
@@ -60,6 +61,9 @@ static ray3 make_ray(const ctgeom *g, double th, int64_t iu, int64_t iv)
     const double P[3] = {r.S[0] - g->sdd * c - ou * s, r.S[1] - g->sdd * s + ou * c, ov};
     for (int k = 0; k < 3; ++k)
         r.d[k] = P[k] - r.S[k];
+    r.c = c;
+    r.s = s;
+    r.ou = ou;
     return r;
 }
 
@@ -79,8 +83,11 @@ static int axis_interval(const ray3 *r, int k, double lo, double hi, double *t0,
     return 1;
 }
 
-/* Length of the ray inside the unit cube of voxel (ix, iy, iz). */
-static double voxel_length(const ctgeom *g, const ray3 *r, int64_t ix, int64_t iy, int64_t iz)
+/* Length of the ray inside the unit cube of voxel (ix, iy, iz); with
+ * tio/kio non-NULL also the entry and exit parameters and the axes that set
+ * them. */
+static double voxel_clip(const ctgeom *g, const ray3 *r, int64_t ix, int64_t iy, int64_t iz,
+                         double *tio, int *kio)
 {
     const double cen[3] = {ix - 0.5 * (g->nx - 1), iy - 0.5 * (g->ny - 1), iz - 0.5 * (g->nz - 1)};
     const int64_t idx[3] = {ix, iy, iz}, n[3] = {g->nx, g->ny, g->nz};
@@ -89,17 +96,28 @@ static double voxel_length(const ctgeom *g, const ray3 *r, int64_t ix, int64_t i
         if (r->d[k] == 0.0 && r->S[k] == cen[k] + 0.5 && idx[k] < n[k] - 1)
             return 0.0;
     double tin = -INFINITY, tout = INFINITY;
+    int kin = -1, kout = -1;
     for (int k = 0; k < 3; ++k) {
         double a, b;
         if (!axis_interval(r, k, cen[k] - 0.5, cen[k] + 0.5, &a, &b))
             return 0.0;
-        if (a > tin)
+        if (a > tin) {
             tin = a;
-        if (b < tout)
+            kin = k;
+        }
+        if (b < tout) {
             tout = b;
+            kout = k;
+        }
     }
     if (tout <= tin)
         return 0.0;
+    if (tio) {
+        tio[0] = tin;
+        tio[1] = tout;
+        kio[0] = kin;
+        kio[1] = kout;
+    }
     const double L = sqrt(r->d[0] * r->d[0] + r->d[1] * r->d[1] + r->d[2] * r->d[2]);
     return (tout - tin) * L;
 }
@@ -109,9 +127,10 @@ static int64_t clampl(int64_t a, int64_t lo, int64_t hi)
     return a < lo ? lo : (a > hi ? hi : a);
 }
 
-/* Calls fn(ctx, voxel flat index within the phase, length) for every voxel
- * the ray passes through with a positive length, in x-slab order. */
-typedef void (*visit_fn)(void *ctx, int64_t v, double len);
+/* Calls fn(ctx, voxel flat index within the phase, length, entry and exit
+ * parameters, their axes) for every voxel the ray passes through with a
+ * positive length, in x-slab order. */
+typedef void (*visit_fn)(void *ctx, int64_t v, double len, const double *tio, const int *kio);
 
 static void ray_voxels(const ctgeom *g, const ray3 *r, visit_fn fn, void *ctx)
 {
@@ -149,9 +168,11 @@ static void ray_voxels(const ctgeom *g, const ray3 *r, visit_fn fn, void *ctx)
         const int64_t z1 = clampl((int64_t)floor((za < zb ? zb : za) + cz + 0.5) + 1, 0, g->nz - 1);
         for (int64_t iy = y0; iy <= y1; ++iy)
             for (int64_t iz = z0; iz <= z1; ++iz) {
-                const double len = voxel_length(g, r, ix, iy, iz);
+                double tio[2];
+                int kio[2];
+                const double len = voxel_clip(g, r, ix, iy, iz, tio, kio);
                 if (len > 0.0)
-                    fn(ctx, (ix * g->ny + iy) * g->nz + iz, len);
+                    fn(ctx, (ix * g->ny + iy) * g->nz + iz, len, tio, kio);
             }
     }
 }
@@ -162,8 +183,10 @@ typedef struct {
     int64_t count;
 } fwd_ctx;
 
-static void fwd_visit(void *c, int64_t v, double len)
+static void fwd_visit(void *c, int64_t v, double len, const double *tio, const int *kio)
 {
+    (void)tio;
+    (void)kio;
     fwd_ctx *f = (fwd_ctx *)c;
     f->sum += len * f->vol[v];
     f->sabs += fabs(f->vol[v]);
@@ -197,8 +220,10 @@ typedef struct {
     double y;
 } bwd_ctx;
 
-static void bwd_visit(void *c, int64_t v, double len)
+static void bwd_visit(void *c, int64_t v, double len, const double *tio, const int *kio)
 {
+    (void)tio;
+    (void)kio;
     bwd_ctx *b = (bwd_ctx *)c;
     b->vol[v] += len * b->y;
     if (b->cnt)
@@ -229,6 +254,137 @@ void ctor_backproject(const ctgeom *g, const double *angles, const double *proj,
                          proj[i * R + rr]};
             ray_voxels(g, &r, bwd_visit, &c);
         }
+}
+
+/* ---- First-order rounding-error model of an FP32 evaluation --------------
+ * For test tolerances only. An FP32 evaluation of the same operator (unit
+ * roundoff u = 2^-24) forms a ray's geometry and every ray-voxel length in
+ * single precision:
+ *   S = sid (cos t, sin t, 0),
+ *   d = (-sdd cos t - ou sin t, -sdd sin t + ou cos t, ov),
+ *   a plane crossing t_k = (p - S_k) / d_k, a length (t_out - t_in) |d|.
+ * With sin and cos within 2 ulp (4u), the absolute errors are at most
+ *   e_S = 5u sid |cos t| (x), 5u sid |sin t| (y), 0 (z),
+ *   e_d = 5u sdd |cos t| + 6u |ou| |sin t| + u |d_x| (x; sin and cos
+ *         swapped for y), u |ov| (z),
+ * so a crossing along axis k is off by at most
+ *   dt_k = (e_S_k + |t_k| e_d_k) / |d_k| + 3u |t_k|
+ * (first order: dt/dS = -1/d, dt/dd = -t/d; then the subtraction, the
+ * reciprocal and the product), |d| by dL = sum_k |d_k| e_d_k / |d| + 3u |d|,
+ * and a length by
+ *   dlen = |d| (dt_in + dt_out) + (t_out - t_in) dL + 2u len.
+ * A crossing nearly parallel to its planes (small |d_k|) is ill-conditioned:
+ * a position error moves it far along the ray. Per ray the bound is the sum
+ * over its voxels of dlen |x_v| plus n_r u sum_v len |x_v| (the n_r-term
+ * sum); per voxel of the transpose the same with the rays through it.
+ * xabs [np][nx][ny][nz] and yabs [np][na][nu][nv] are |x| and |y|; eproj
+ * (per ray) and evol (per voxel) receive the bounds; either may be NULL. */
+static double pair_error(const ctgeom *g, const ray3 *r, double len, const double *tio,
+                         const int *kio)
+{
+    const double u = 0x1.0p-24;
+    const double ac = fabs(r->c), as = fabs(r->s), aou = fabs(r->ou);
+    const double eS[3] = {5 * u * g->sid * ac, 5 * u * g->sid * as, 0.0};
+    const double ed[3] = {5 * u * g->sdd * ac + 6 * u * aou * as + u * fabs(r->d[0]),
+                          5 * u * g->sdd * as + 6 * u * aou * ac + u * fabs(r->d[1]),
+                          u * fabs(r->d[2])};
+    const double L = sqrt(r->d[0] * r->d[0] + r->d[1] * r->d[1] + r->d[2] * r->d[2]);
+    double dt = 0.0;
+    for (int j = 0; j < 2; ++j) {
+        const int k = kio[j];
+        const double t = fabs(tio[j]);
+        dt += (eS[k] + t * ed[k]) / fabs(r->d[k]) + 3 * u * t;
+    }
+    const double dL = (fabs(r->d[0]) * ed[0] + fabs(r->d[1]) * ed[1] + fabs(r->d[2]) * ed[2]) / L +
+                      3 * u * L;
+    return L * dt + (tio[1] - tio[0]) * dL + 2 * u * len;
+}
+
+typedef struct {
+    const ctgeom *g;
+    ray3 r;
+    const double *xabs;
+    double e, slx, n;
+} efwd_ctx;
+
+static void efwd_visit(void *c, int64_t v, double len, const double *tio, const int *kio)
+{
+    efwd_ctx *f = (efwd_ctx *)c;
+    f->e += f->xabs[v] * pair_error(f->g, &f->r, len, tio, kio);
+    f->slx += len * f->xabs[v];
+    f->n += 1.0;
+}
+
+typedef struct {
+    const ctgeom *g;
+    ray3 r;
+    double *e, *sly, *n;
+    double yabs;
+} ebwd_ctx;
+
+static void ebwd_visit(void *c, int64_t v, double len, const double *tio, const int *kio)
+{
+    ebwd_ctx *b = (ebwd_ctx *)c;
+    b->e[v] += b->yabs * pair_error(b->g, &b->r, len, tio, kio);
+    b->sly[v] += len * b->yabs;
+    b->n[v] += 1.0;
+}
+
+void ctor_error_model(const ctgeom *g, const double *angles, const double *xabs,
+                      const double *yabs, double *eproj, double *evol)
+{
+    const double u = 0x1.0p-24;
+    const int64_t N = g->nx * g->ny * g->nz;
+    const int64_t R = g->na * g->nu * g->nv;
+    if (eproj) {
+#pragma omp parallel for schedule(dynamic, 16)
+        for (int64_t t = 0; t < g->np * R; ++t) {
+            const int64_t i = t / R, rr = t - i * R;
+            const int64_t a = rr / (g->nu * g->nv), iu = (rr / g->nv) % g->nu, iv = rr % g->nv;
+            efwd_ctx c;
+            c.g = g;
+            c.r = make_ray(g, angles[i * g->na + a], iu, iv);
+            c.xabs = xabs + i * N;
+            c.e = c.slx = c.n = 0.0;
+            ray_voxels(g, &c.r, efwd_visit, &c);
+            eproj[t] = c.e + c.n * u * c.slx;
+        }
+    }
+    if (evol) {
+        double *sly = (double *)calloc((size_t)(g->np * N), sizeof(double));
+        double *cnt = (double *)calloc((size_t)(g->np * N), sizeof(double));
+        memset(evol, 0, sizeof(double) * g->np * N);
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int64_t i = 0; i < g->np; ++i)
+            for (int64_t rr = 0; rr < R; ++rr) {
+                const int64_t a = rr / (g->nu * g->nv), iu = (rr / g->nv) % g->nu, iv = rr % g->nv;
+                ebwd_ctx c;
+                c.g = g;
+                c.e = evol + i * N;
+                c.sly = sly + i * N;
+                c.n = cnt + i * N;
+                c.yabs = yabs[i * R + rr];
+                c.r = make_ray(g, angles[i * g->na + a], iu, iv);
+                ray_voxels(g, &c.r, ebwd_visit, &c);
+            }
+        for (int64_t v = 0; v < g->np * N; ++v)
+            evol[v] += cnt[v] * u * sly[v];
+        free(sly);
+        free(cnt);
+    }
+}
+
+/* One pair of the model: the exact length of ray (th, iu, iv) in voxel
+ * (ix, iy, iz) in *len, and its FP32 error bound dlen as the return value
+ * (0 where the length is 0). */
+double ctor_pair_error(const ctgeom *g, double th, int64_t iu, int64_t iv, int64_t ix,
+                       int64_t iy, int64_t iz, double *len)
+{
+    const ray3 r = make_ray(g, th, iu, iv);
+    double tio[2];
+    int kio[2];
+    *len = voxel_clip(g, &r, ix, iy, iz, tio, kio);
+    return *len > 0.0 ? pair_error(g, &r, *len, tio, kio) : 0.0;
 }
 
 /* Length of ray (phase angle th, pixel iu, iv) inside the axis-aligned box

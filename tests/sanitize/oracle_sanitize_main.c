@@ -49,6 +49,10 @@ void ctor_backproject(const ctgeom *, const double *, const double *, double *, 
                       double *);
 double ctor_box_chord(const ctgeom *, double, int64_t, int64_t, const double *,
                       const double *);
+void ctor_error_model(const ctgeom *, const double *, const double *, const double *, double *,
+                      double *);
+double ctor_pair_error(const ctgeom *, double, int64_t, int64_t, int64_t, int64_t, int64_t,
+                       double *);
 
 static int failures = 0;
 #define CHECK(c, ...)                                    \
@@ -174,6 +178,18 @@ static void ct_case(int64_t nx, int64_t ny, int64_t nz, int64_t nu, int64_t nv, 
     for (int64_t k = 0; k < 2 * N; ++k)
         r += x[k] * b[k];
     CHECK(fabs(l - r) <= 1e-10 * fabs(l), "adjointness %.17g vs %.17g", l, r);
+    /* FP32 error model: both outputs, then each alone; one pair per voxel */
+    ctor_error_model(&g, ang, x, y, pc, bc);
+    ctor_error_model(&g, ang, x, NULL, ps, NULL);
+    ctor_error_model(&g, ang, NULL, y, NULL, bs);
+    for (int64_t k = 0; k < 2 * R; ++k)
+        CHECK(pc[k] >= 0.0 && pc[k] == ps[k], "projection bound %.17g", pc[k]);
+    for (int64_t ix = 0; ix < nx; ++ix)
+        for (int64_t iz = 0; iz < nz; ++iz) {
+            double len;
+            const double e = ctor_pair_error(&g, 0.7, nu / 2, nv / 2, ix, ny / 2, iz, &len);
+            CHECK(len >= 0.0 && e >= 0.0, "pair %.17g %.17g", len, e);
+        }
     const double lo[3] = {-2.0, -1.5, -1.0}, hi[3] = {2.0, 1.5, 1.0};
     for (int64_t iu = 0; iu < nu; ++iu)
         for (int64_t iv = 0; iv < nv; ++iv) {

@@ -149,3 +149,109 @@ def test_tnlm_r_fixed_point_and_positivity():
     y2 = y + rng.normal(0, 0.5, size=y.shape)
     f2 = ct.tnlm_r(g, ang, y2, np.zeros(g.vol_shape), 0.5, 1, 1, 0.05, outer=2, cg_iters=3)
     assert f2.min() >= 0.0 and f2.max() > 0.0
+
+
+def _f32_length(g, th, iu, iv, voxel):
+    """The length of ray (th, iu, iv) in a voxel's cube evaluated with float32
+    operations, the geometry formed from float32 sin and cos as a
+    single-precision kernel forms it."""
+    f = np.float32
+    th = f(th)
+    s, c = f(np.sin(np.float64(th))), f(np.cos(np.float64(th)))
+    ou = f(f(iu - 0.5 * (g.nu - 1)) * f(g.du))
+    ov = f(f(iv - 0.5 * (g.nv - 1)) * f(g.dv))
+    S = (f(g.sid) * c, f(g.sid) * s, f(0))
+    d = (f(-f(g.sdd) * c - ou * s), f(-f(g.sdd) * s + ou * c), ov)
+    n = (g.nx, g.ny, g.nz)
+    tin, tout = f(-np.inf), f(np.inf)
+    for k in range(3):
+        cen = f(voxel[k] - 0.5 * (n[k] - 1))
+        if d[k] == 0:
+            if not (cen - f(0.5) <= S[k] < cen + f(0.5)):
+                return 0.0
+            continue
+        inv = f(1) / d[k]
+        t0, t1 = ((cen - f(0.5)) - S[k]) * inv, ((cen + f(0.5)) - S[k]) * inv
+        tin, tout = max(tin, min(t0, t1)), min(tout, max(t0, t1))
+    L = f(np.sqrt(f(d[0] * d[0] + d[1] * d[1] + d[2] * d[2])))
+    return float((tout - tin) * L) if tout > tin else 0.0
+
+
+def test_fp32_error_model_bounds_float32_lengths_at_shallow_crossings():
+    """The per-pair FP32 error model (ct.pair_error, behind ct.error_model)
+    bounds the error of a float32 evaluation of each ray-voxel length, also
+    where a ray leaves a voxel through a face it is nearly parallel to: in
+    the recon128 scan geometry (source 500 voxels from the isocentre) the
+    rays of detector columns 49-53 at 84 degrees run almost parallel to the
+    x faces near x = 52, and a float32 position error of one ulp moves their
+    crossing far along the ray: errors of ~1e-3 of the length, thousands of
+    times a length's own rounding, which the model's 1/|d_k| amplification
+    must (and does) cover."""
+    from phantom.breathing import CT_WORKLOADS
+    w = CT_WORKLOADS["recon128"]
+    g = ct.CTGeom(1, w.nx, w.ny, w.nz, w.nu, w.nv, 1, w.sid, w.sdd, w.du, w.dv)
+    th = float(np.float32(ct_angles(w.np_, w.na)[0, 7]))
+    worst_ratio, worst_rel = 0.0, 0.0
+    for iu in range(49, 54):
+        for iv in (300, 303, 306):
+            for voxel in ((116, 32, 77), (115, 32, 77), (116, 33, 77), (117, 31, 77)):
+                ln, b = ct.pair_error(g, th, iu, iv, voxel)
+                if ln == 0.0:
+                    continue
+                err = abs(_f32_length(g, th, iu, iv, voxel) - ln)
+                worst_ratio = max(worst_ratio, err / b)
+                worst_rel = max(worst_rel, err / ln)
+    print("largest error / bound", worst_ratio, "largest relative error", worst_rel)
+    assert worst_ratio <= 1.0
+    assert worst_rel >= 1e-3  # the amplified regime is reached
+
+
+def test_fp32_error_model_bounds_a_float32_evaluation():
+    """The first-order FP32 error model of the projector (ct.error_model)
+    bounds the error of an actual float32 evaluation of the same lengths:
+    every ray's sum over all voxels of (t_out - t_in) |d| |x_v|, each length
+    clipped against the voxel's cube with float32 operations (geometry from
+    float32 sin and cos, as a single-precision kernel forms it), against the
+    FP64 oracle, element by element; a long source distance makes the
+    near-parallel crossings (the model's 1/|d_k| amplification) matter."""
+    n, nu, nv = 24, 40, 30
+    g = ct.CTGeom(1, n, n, n, nu, nv, 3, 300.0, 460.0, 0.9, 0.9)
+    # near 90 degrees the x component of the central rays' directions
+    # changes sign on the detector: near-parallel x crossings
+    ang = np.array([[0.3, 1.55, 1.5625]])
+    x = np.random.default_rng(5).uniform(0.0, 1.0, size=g.vol_shape)
+    ref = ct.project(g, ang, x)
+    bound = ct.error_model(g, ang, xabs=np.abs(x))[0]
+    f = np.float32
+    c0 = (np.arange(n, dtype=f) - f(0.5 * (n - 1)))
+    X, Y, Z = np.meshgrid(c0, c0, c0, indexing="ij")
+    xv = x[0].astype(f)
+    worst = 0.0
+    for a in range(g.na):
+        th = f(ang[0, a])
+        s, c = f(np.sin(np.float64(th))), f(np.cos(np.float64(th)))
+        S = (f(g.sid) * c, f(g.sid) * s, f(0))
+        for iu in range(nu):
+            ou = f(f(iu - 0.5 * (nu - 1)) * f(g.du))
+            for iv in range(0, nv, 3):
+                ov = f(f(iv - 0.5 * (nv - 1)) * f(g.dv))
+                d = (f(-f(g.sdd) * c - ou * s), f(-f(g.sdd) * s + ou * c), ov)
+                tin = np.full(X.shape, -np.inf, dtype=f)
+                tout = np.full(X.shape, np.inf, dtype=f)
+                ok = np.ones(X.shape, dtype=bool)
+                for C, Sk, dk in ((X, S[0], d[0]), (Y, S[1], d[1]), (Z, S[2], d[2])):
+                    if dk == 0:
+                        ok &= (Sk >= C - f(0.5)) & (Sk < C + f(0.5))
+                        continue
+                    inv = f(1) / dk
+                    t0 = ((C - f(0.5)) - Sk) * inv
+                    t1 = ((C + f(0.5)) - Sk) * inv
+                    tin = np.maximum(tin, np.minimum(t0, t1))
+                    tout = np.minimum(tout, np.maximum(t0, t1))
+                L = np.sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2], dtype=f)
+                ln = np.where(ok & (tout > tin), (tout - tin) * L, f(0))
+                got = float(np.sum(ln.astype(np.float64) * xv))
+                r = abs(got - ref[0, a, iu, iv]) / bound[0, a, iu, iv]
+                worst = max(worst, r)
+    print("largest error / bound", worst)
+    assert 0.0 < worst <= 1.0, worst

@@ -2,15 +2,14 @@
 of Sec. 2.3): the cone-beam projector, its transpose, CGLS and the TNLM-R
 driver against the FP64 oracle (oracle/ct.py), through the C ABI.
 
-Tolerances are derived from the FP32 arithmetic of the kernels: a ray's
-entry and exit parameters along each axis carry a relative rounding error
-of a few units, so every ray-voxel length is off by at most about
-8 u (sid + R) (R the volume's half-diagonal: the distance from the source to
-the far side of the volume, where the parameters are largest), and the sum
-of n terms adds n u sum |a x|. Per ray r:
-    |dP x|_r <= u (8 (sid + R) sum_{v on r} |x_v| + n_r (P|x|)_r),
-and per voxel v for the transpose with the roles of rays and voxels
-swapped. Comparisons are normwise at max(1e-5, max bound / max|ref|).
+Tolerances come from a first-order model of the kernels' FP32 arithmetic
+(oracle.ct.error_model): the ray's source and direction carry the rounding
+of sin, cos and their products, every plane crossing t = (p - S_k) / d_k
+inherits it amplified by 1/|d_k| (a crossing nearly parallel to its planes is
+ill-conditioned), and each ray-voxel length (t_out - t_in) |d| the errors of
+its two crossings; the n-term sums add n u sum |a x|. Per ray for P, per
+voxel for P^T. Comparisons are normwise at max(1e-5, max bound / max|ref|),
+and every element must also lie within its own bound.
 """
 import numpy as np
 import pytest
@@ -35,17 +34,18 @@ def setup(nx, ny, nz, nu, nv, na, np_, sid, sdd, du, dv, seed=0, angles=None):
 
 
 def fwd_bound(og, ang, x):
-    R = 0.5 * np.sqrt(og.nx ** 2 + og.ny ** 2 + og.nz ** 2)
-    _, cnt, sab = OCT.project(og, ang, x, want_stats=True)
-    pabs = OCT.project(og, ang, np.abs(x))
-    return U32 * (8 * (og.sid + R) * sab + cnt * pabs)
+    return OCT.error_model(og, ang, xabs=np.abs(x))[0]
 
 
 def bwd_bound(og, ang, y):
-    R = 0.5 * np.sqrt(og.nx ** 2 + og.ny ** 2 + og.nz ** 2)
-    _, cnt, sab = OCT.backproject(og, ang, y, want_stats=True)
-    babs = OCT.backproject(og, ang, np.abs(y))
-    return U32 * (8 * (og.sid + R) * sab + cnt * babs)
+    return OCT.error_model(og, ang, yabs=np.abs(y))[1]
+
+
+def assert_within(got, ref, bound, what):
+    """Every element within its own first-order bound."""
+    r = np.abs(np.asarray(got, dtype=np.float64) - ref) / np.maximum(bound, 1e-300)
+    say(f"  {what}: largest error / element bound {r.max():.3f}")
+    assert r.max() <= 1.0, f"{what}: error exceeds its element bound ({r.max():.3f})"
 
 
 GEOMS = [
@@ -80,8 +80,11 @@ def test_projector_and_transpose_match_the_oracle(gm):
     torch.cuda.synchronize()
     bp = fwd_bound(og, ang, x)
     bb = bwd_bound(og, ang, y)
-    assert_close(host(p), OCT.project(og, ang, x), "P x", bp)
-    assert_close(host(b), OCT.backproject(og, ang, y), "P^T y", bb)
+    pr, br = OCT.project(og, ang, x), OCT.backproject(og, ang, y)
+    assert_close(host(p), pr, "P x", bp)
+    assert_close(host(b), br, "P^T y", bb)
+    assert_within(host(p), pr, bp, "P x")
+    assert_within(host(b), br, bb, "P^T y")
     # adjointness of the two GPU operators, within what their bounds allow
     lhs = float(np.vdot(host(p), y))
     rhs = float(np.vdot(x, host(b)))
@@ -195,3 +198,46 @@ def test_tnlm_r_driver_composes_cgls_jacobi_and_positivity():
     say(f"  rms error against the truth per outer iteration: {errs}")
     assert errs[-1] < errs[0]
     assert torch.equal(f, stages[-1][1])
+
+
+def test_recon128_at_full_size_on_sampled_projections():
+    """The recon128 workload at full size, in the launch configuration the
+    benchmark times (10 x 128^3 voxels, 10 x 30 projections of 512 x 512):
+    every ray of two of the 300 projections against the oracle, and the
+    transpose of a projection stack that is zero except at those two
+    projections against the oracle's transpose of them over every voxel of
+    their phases (the other phases must come out exactly zero)."""
+    from phantom.breathing import CT_WORKLOADS
+    w = CT_WORKLOADS["recon128"]
+    a32 = np.ascontiguousarray(ct_angles(w.np_, w.na), dtype=np.float32)
+    at = torch.from_numpy(a32).to(device())
+    geo = tnlm.ct.Geometry(w.nu, w.nv, w.sid, w.sdd, w.du, w.dv)
+    og = OCT.CTGeom(1, w.nx, w.ny, w.nz, w.nu, w.nv, 1, w.sid, w.sdd, w.du, w.dv)
+    shape = (w.np_, w.nx, w.ny, w.nz)
+    rng = np.random.default_rng(11)
+    x = rng.uniform(0.0, 1.0, size=shape).astype(np.float32)
+    say("recon128 projector, full size")
+    p = tnlm.ct.project(torch.from_numpy(x).to(device()), geo, at)
+    picks = [(0, 7), (6, 22)]  # (phase, angle index within the phase)
+    for i, a in picks:
+        sel = a32[i:i + 1, a:a + 1].astype(np.float64)
+        xi = x[i:i + 1].astype(np.float64)
+        ref, bnd = OCT.project(og, sel, xi), fwd_bound(og, sel, xi)
+        got = host(p[i:i + 1, a:a + 1])
+        assert_close(got, ref, f"recon128 P x, phase {i} angle {a}", bnd)
+        assert_within(got, ref, bnd, f"recon128 P x, phase {i} angle {a}")
+    say("recon128 transpose, full size")
+    y = torch.zeros((w.np_, w.na, w.nu, w.nv), dtype=torch.float32, device=device())
+    ys = {}
+    for i, a in picks:
+        ys[i] = rng.normal(0.0, 1.0, size=(1, 1, w.nu, w.nv)).astype(np.float32)
+        y[i, a] = torch.from_numpy(ys[i][0, 0]).to(device())
+    b = host(tnlm.ct.backproject(y, geo, at, shape))
+    for i, a in picks:
+        sel = a32[i:i + 1, a:a + 1].astype(np.float64)
+        yi = ys[i].astype(np.float64)
+        ref, bnd = OCT.backproject(og, sel, yi), bwd_bound(og, sel, yi)
+        assert_close(b[i:i + 1], ref, f"recon128 P^T y, phase {i} angle {a}", bnd)
+        assert_within(b[i:i + 1], ref, bnd, f"recon128 P^T y, phase {i} angle {a}")
+    others = [k for k in range(w.np_) if k not in dict(picks)]
+    assert np.all(b[others] == 0.0)
