@@ -270,7 +270,8 @@ void ctor_backproject(const ctgeom *g, const double *angles, const double *proj,
  * so a crossing along axis k is off by at most
  *   dt_k = (e_S_k + |t_k| e_d_k) / |d_k| + 3u |t_k|
  * (first order: dt/dS = -1/d, dt/dd = -t/d; then the subtraction, the
- * reciprocal and the product), |d| by dL = sum_k |d_k| e_d_k / |d| + 3u |d|,
+ * reciprocal and the product), |d| by dL = sum_k |d_k| e_d_k / |d| + 4u |d|
+ * (the sum of squares, then a square root within 1 ulp),
  * and a length by
  *   dlen = |d| (dt_in + dt_out) + (t_out - t_in) dL + 2u len.
  * A crossing nearly parallel to its planes (small |d_k|) is ill-conditioned:
@@ -296,7 +297,7 @@ static double pair_error(const ctgeom *g, const ray3 *r, double len, const doubl
         dt += (eS[k] + t * ed[k]) / fabs(r->d[k]) + 3 * u * t;
     }
     const double dL = (fabs(r->d[0]) * ed[0] + fabs(r->d[1]) * ed[1] + fabs(r->d[2]) * ed[2]) / L +
-                      3 * u * L;
+                      4 * u * L;
     return L * dt + (tio[1] - tio[0]) * dL + 2 * u * len;
 }
 

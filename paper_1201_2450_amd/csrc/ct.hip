@@ -273,7 +273,9 @@ __global__ void __launch_bounds__(kBlock) backproject_kernel(CTG g, const float 
                 }
                 const float tin = fmaxf(txy0, z0), tout = fminf(txy1, z1);
                 if (hxy && zin && tout > tin) {
-                    const float L = sqrtf(d0 * d0 + d1 * d1 + ov * ov);
+                    // the hardware square root (within 1 ulp; the argument is
+                    // at least sdd^2, far from denormals)
+                    const float L = __builtin_amdgcn_sqrtf(d0 * d0 + d1 * d1 + ov * ov);
                     acc = fmaf((tout - tin) * L, pa[(int64_t)iu * g.nv + iv], acc);
                 }
             }
