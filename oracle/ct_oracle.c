@@ -268,9 +268,9 @@ void ctor_backproject(const ctgeom *g, const double *angles, const double *proj,
  *   e_d = 5u sdd |cos t| + 6u |ou| |sin t| + u |d_x| (x; sin and cos
  *         swapped for y), u |ov| (z),
  * so a crossing along axis k is off by at most
- *   dt_k = (e_S_k + |t_k| e_d_k) / |d_k| + 3u |t_k|
- * (first order: dt/dS = -1/d, dt/dd = -t/d; then the subtraction, the
- * reciprocal and the product), |d| by dL = sum_k |d_k| e_d_k / |d| + 4u |d|
+ *   dt_k = (e_S_k + |t_k| e_d_k) / |d_k| + 4u |t_k|
+ * (first order: dt/dS = -1/d, dt/dd = -t/d; then the subtraction, a
+ * reciprocal within one ulp and the product), |d| by dL = sum_k |d_k| e_d_k / |d| + 4u |d|
  * (the sum of squares, then a square root within 1 ulp),
  * and a length by
  *   dlen = |d| (dt_in + dt_out) + (t_out - t_in) dL + 2u len.
@@ -294,7 +294,7 @@ static double pair_error(const ctgeom *g, const ray3 *r, double len, const doubl
     for (int j = 0; j < 2; ++j) {
         const int k = kio[j];
         const double t = fabs(tio[j]);
-        dt += (eS[k] + t * ed[k]) / fabs(r->d[k]) + 3 * u * t;
+        dt += (eS[k] + t * ed[k]) / fabs(r->d[k]) + 4 * u * t;
     }
     const double dL = (fabs(r->d[0]) * ed[0] + fabs(r->d[1]) * ed[1] + fabs(r->d[2]) * ed[2]) / L +
                       4 * u * L;
