@@ -269,25 +269,45 @@ __global__ void __launch_bounds__(kBlock) backproject_kernel(CTG g, const float 
             hxy = vslab(S1, d1, cen[1] - 0.5f, cen[1] + 0.5f, y == g.ny - 1, a0, a1) && hxy;
             txy0 = fmaxf(txy0, a0);
             txy1 = fminf(txy1, a1);
-            for (int iv = v0; iv <= v1; ++iv) {
-                const float ov = (iv - vcen) * g.dv;
-                float z0, z1;
-                bool zin;
-                if (TAB) {
-                    const float inv = tab[2 * nang + iv];
-                    const float za = zlo * inv, zb = zhi * inv;
-                    z0 = ov == 0.f ? -INFINITY : fminf(za, zb);
-                    z1 = ov == 0.f ? INFINITY : fmaxf(za, zb);
-                    zin = ov != 0.f || zin0;
-                } else {
-                    zin = vslab(0.f, ov, zlo, zhi, z == g.nz - 1, z0, z1);
+            // a column whose rays miss the voxel's x-y extent adds nothing
+            if (!hxy || !(txy1 > txy0))
+                continue;
+            const float cx0 = __builtin_canonicalizef(txy0), cx1 = __builtin_canonicalizef(txy1);
+            const float d01 = d0 * d0 + d1 * d1;
+            const float *pcol = pa + (int64_t)iu * g.nv;
+            auto add = [&](int iv, float ov, float z0, float z1) {
+                const float tin = fmaxf(cx0, z0), tout = fminf(cx1, z1);
+                if (tout > tin) {
+                    // the hardware square root (within 1 ulp; the argument
+                    // is at least sdd^2, far from denormals)
+                    const float L = __builtin_amdgcn_sqrtf(d01 + ov * ov);
+                    acc = fmaf((tout - tin) * L, pcol[iv], acc);
                 }
-                const float tin = fmaxf(txy0, z0), tout = fminf(txy1, z1);
-                if (hxy && zin && tout > tin) {
-                    // the hardware square root (within 1 ulp; the argument is
-                    // at least sdd^2, far from denormals)
-                    const float L = __builtin_amdgcn_sqrtf(d0 * d0 + d1 * d1 + ov * ov);
-                    acc = fmaf((tout - tin) * L, pa[(int64_t)iu * g.nv + iv], acc);
+            };
+            if (TAB) {
+                // rows below the detector centre (ov < 0: the ray enters the
+                // z slab at zhi), the centre row of an odd nv (ov = 0: no z
+                // bound), rows above (enters at zlo); in row order
+                const float *rinv = tab + 2 * nang;
+                const int ivc = (g.nv - 1) / 2;
+                const bool odd = (g.nv & 1) != 0;
+                const int neg_end = min(v1, odd ? ivc - 1 : ivc);
+                for (int iv = v0; iv <= neg_end; ++iv) {
+                    const float inv = rinv[iv];
+                    add(iv, (iv - vcen) * g.dv, zhi * inv, zlo * inv);
+                }
+                if (odd && zin0 && ivc >= v0 && ivc <= v1)
+                    add(ivc, 0.f, -INFINITY, INFINITY);
+                for (int iv = max(v0, ivc + 1); iv <= v1; ++iv) {
+                    const float inv = rinv[iv];
+                    add(iv, (iv - vcen) * g.dv, zlo * inv, zhi * inv);
+                }
+            } else {
+                for (int iv = v0; iv <= v1; ++iv) {
+                    const float ov = (iv - vcen) * g.dv;
+                    float z0, z1;
+                    if (vslab(0.f, ov, zlo, zhi, z == g.nz - 1, z0, z1))
+                        add(iv, ov, z0, z1);
                 }
             }
         }
