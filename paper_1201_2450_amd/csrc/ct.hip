@@ -173,11 +173,38 @@ __global__ void __launch_bounds__(kBlock) project_kernel(CTG g, const float *vol
 
 // The transpose reads two per-block tables from LDS when they fit
 // (kTabBytes): the sine and cosine of every angle of the phases the block's
-// voxels belong to, and for every detector row iv the reciprocal of the
-// ray's axial component (iv - (nv-1)/2) dv, which sets the z slab of every
-// pixel's clipping. Both hold the values the threads would compute
-// themselves, so the results do not depend on whether they are used.
+// voxels belong to, and for every detector row iv the ray's axial component
+// ov = (iv - (nv-1)/2) dv and the z slab's parameters: with r = 1/ov and the
+// voxel's z range [zlo, zlo + 1], the entry and exit are fma(zlo, r, c0) and
+// fma(zlo, r, c1), (c0, c1) = (r, 0) below the detector centre (ov < 0) and
+// (0, r) above it, i.e. zhi r and zlo r or the reverse, each rounded once;
+// the centre row of an odd nv (ov = 0, no z bound) has r = 0 and (c0, c1) =
+// (-inf, +inf). They hold the values the threads would compute themselves, so
+// the results do not depend on whether the tables are used.
 constexpr int kTabBytes = 32 * 1024;
+
+// max and min of two floats as single instructions: fmaxf/fminf re-quiet
+// (canonicalise) loop-invariant operands on every iteration; the operands
+// here are never NaN
+__device__ __forceinline__ float vmaxf(float a, float b)
+{
+    float r;
+    asm("v_max_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+__device__ __forceinline__ float vminf(float a, float b)
+{
+    float r;
+    asm("v_min_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
+// start (in floats) of the per-row table, after nang (sin, cos) pairs and
+// aligned for 16-byte reads
+__host__ __device__ inline int row_tab_offset(int nang)
+{
+    return (2 * nang + 3) & ~3;
+}
 
 // phases a block of kBlock consecutive voxels can touch
 __host__ __device__ inline int block_phase_span(const CTG &g)
@@ -189,7 +216,9 @@ __host__ __device__ inline int block_phase_span(const CTG &g)
 template <bool TAB>
 __global__ void __launch_bounds__(kBlock) backproject_kernel(CTG g, const float *proj, float *vol)
 {
-    extern __shared__ float tab[];  // [span][na] (sin, cos) pairs, then [nv]
+    // [span][na] (sin, cos) pairs, then from a 16-byte boundary [nv] (r, c0, c1, ov)
+    extern __shared__ float4 tab4[];
+    float *tab = (float *)tab4;
     const int64_t tb = (int64_t)blockIdx.x * kBlock;
     const int ib = (int)(tb / g.N);  // first phase of the block
     const int nang = TAB ? block_phase_span(g) * g.na : 0;
@@ -203,8 +232,15 @@ __global__ void __launch_bounds__(kBlock) backproject_kernel(CTG g, const float 
             tab[2 * k] = sn;
             tab[2 * k + 1] = cs;
         }
-        for (int k = threadIdx.x; k < g.nv; k += kBlock)
-            tab[2 * nang + k] = 1.f / ((k - vcen) * g.dv);  // +-inf on a centre row
+        for (int k = threadIdx.x; k < g.nv; k += kBlock) {
+            const float ov = (k - vcen) * g.dv;
+            const float r = 1.f / ov;
+            float *row = tab + row_tab_offset(nang) + 4 * k;
+            row[0] = ov == 0.f ? 0.f : r;
+            row[1] = ov == 0.f ? -INFINITY : (ov < 0.f ? r : 0.f);
+            row[2] = ov == 0.f ? INFINITY : (ov < 0.f ? 0.f : r);
+            row[3] = ov;
+        }
         __syncthreads();
     }
     const int64_t t = tb + threadIdx.x;
@@ -255,6 +291,10 @@ __global__ void __launch_bounds__(kBlock) backproject_kernel(CTG g, const float 
         // clamped in float before converting
         const int u0 = (int)fmaxf(0.f, ceilf(umin)), u1 = (int)fminf(g.nu - 1.f, floorf(umax));
         const int v0 = (int)fmaxf(0.f, ceilf(vmin)), v1 = (int)fminf(g.nv - 1.f, floorf(vmax));
+        // the centre row of an odd nv (rays in the plane z = 0) reaches this
+        // voxel only if its half-open z range holds 0; where it does not, that
+        // row can only be the footprint's last (the voxel's top face is z = 0)
+        const int v1c = (TAB && (g.nv & 1) && !zin0 && v1 == (g.nv - 1) / 2) ? v1 - 1 : v1;
         const float *pa = proj + ((int64_t)i * g.na + a) * g.nu * g.nv;
         for (int iu = u0; iu <= u1; ++iu) {
             // the ray of pixel (iu, iv): source S = sid (c, s, 0), direction
@@ -272,11 +312,10 @@ __global__ void __launch_bounds__(kBlock) backproject_kernel(CTG g, const float 
             // a column whose rays miss the voxel's x-y extent adds nothing
             if (!hxy || !(txy1 > txy0))
                 continue;
-            const float cx0 = __builtin_canonicalizef(txy0), cx1 = __builtin_canonicalizef(txy1);
             const float d01 = d0 * d0 + d1 * d1;
             const float *pcol = pa + (int64_t)iu * g.nv;
             auto add = [&](int iv, float ov, float z0, float z1) {
-                const float tin = fmaxf(cx0, z0), tout = fminf(cx1, z1);
+                const float tin = vmaxf(txy0, z0), tout = vminf(txy1, z1);
                 if (tout > tin) {
                     // the hardware square root (within 1 ulp; the argument
                     // is at least sdd^2, far from denormals)
@@ -285,22 +324,10 @@ __global__ void __launch_bounds__(kBlock) backproject_kernel(CTG g, const float 
                 }
             };
             if (TAB) {
-                // rows below the detector centre (ov < 0: the ray enters the
-                // z slab at zhi), the centre row of an odd nv (ov = 0: no z
-                // bound), rows above (enters at zlo); in row order
-                const float *rinv = tab + 2 * nang;
-                const int ivc = (g.nv - 1) / 2;
-                const bool odd = (g.nv & 1) != 0;
-                const int neg_end = min(v1, odd ? ivc - 1 : ivc);
-                for (int iv = v0; iv <= neg_end; ++iv) {
-                    const float inv = rinv[iv];
-                    add(iv, (iv - vcen) * g.dv, zhi * inv, zlo * inv);
-                }
-                if (odd && zin0 && ivc >= v0 && ivc <= v1)
-                    add(ivc, 0.f, -INFINITY, INFINITY);
-                for (int iv = max(v0, ivc + 1); iv <= v1; ++iv) {
-                    const float inv = rinv[iv];
-                    add(iv, (iv - vcen) * g.dv, zlo * inv, zhi * inv);
+                const float4 *rtab = (const float4 *)(tab + row_tab_offset(nang));
+                for (int iv = v0; iv <= v1c; ++iv) {
+                    const float4 r = rtab[iv];
+                    add(iv, r.w, fmaf(zlo, r.x, r.y), fmaf(zlo, r.x, r.z));
                 }
             } else {
                 for (int iv = v0; iv <= v1; ++iv) {
@@ -503,7 +530,9 @@ hipError_t ct_backproject(const tnlm_ct_geom *p, const float *proj, float *vol, 
     const CTG g = make(p);
     const int64_t n = (int64_t)g.np * g.N;
     const int64_t grid = (n + kBlock - 1) / kBlock;
-    const int64_t tab = ((int64_t)block_phase_span(g) * g.na * 2 + g.nv) * sizeof(float);
+    const int64_t nang = (int64_t)block_phase_span(g) * g.na;
+    const int64_t tab = nang > (1 << 20) ? INT64_MAX
+                                         : ((int64_t)row_tab_offset((int)nang) + 4 * g.nv) * sizeof(float);
     if (tab <= kTabBytes)
         backproject_kernel<true><<<grid, kBlock, (size_t)tab, s>>>(g, proj, vol);
     else
