@@ -45,8 +45,9 @@ def _compile(src: str) -> str:
 
 
 def _runtime_dir() -> str:
-    """Directory of an unversioned libamdhip64.so without a SONAME (PyTorch's
-    bundled runtime), so the recorded dependency is 'libamdhip64.so'."""
+    """Directory of PyTorch's bundled HIP runtime (else the system ROCm's):
+    the link records the runtime's SONAME (libamdhip64.so.7), which a torch
+    process has already loaded from there."""
     import importlib.util
     spec = importlib.util.find_spec("torch")
     if spec and spec.origin:
@@ -63,11 +64,11 @@ def build(verbose: bool = False) -> str:
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp%d" % os.getpid()
-    # Link against the HIP runtime by its unversioned name, so that inside a
-    # process that already loaded PyTorch's bundled ROCm runtime the library
-    # binds to that same runtime (one HIP/HSA stack per process: device
-    # pointers and streams from torch stay valid); standalone it resolves to
-    # the system ROCm.
+    # Link against the HIP runtime by its SONAME, so that inside a process
+    # that already loaded PyTorch's bundled ROCm runtime the library binds to
+    # that same runtime (one HIP/HSA stack per process: device pointers and
+    # streams from torch stay valid); standalone it resolves to the system
+    # ROCm.
     cmd = ["g++", "-shared", "-fPIC", "-o", tmp, *objs, "-L" + _runtime_dir(),
            "-l:libamdhip64.so", "-Wl,--no-undefined", "-lstdc++", "-lm"]
     r = subprocess.run(cmd, capture_output=True, text=True)
