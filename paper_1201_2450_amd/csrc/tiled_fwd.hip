@@ -201,6 +201,7 @@ __global__ void __launch_bounds__(C::THREADS) fwd_tiled_kernel(Geo g, FwdArgs a,
 
     const int64_t N = g.N;
     const int nx = g.nx, ny = g.ny, nz = g.nz;
+    const float nc2 = in_vgpr(-g.c2);  // the exponent's factor, in a vector register
     const T *u = (const T *)a.u;
     const T *f = (const T *)a.f;
     // masks are needed where some candidate of some output of this wave
@@ -305,7 +306,7 @@ __global__ void __launch_bounds__(C::THREADS) fwd_tiled_kernel(Geo g, FwdArgs a,
                     if (pass == PASS_MIN) {
                         A.N[xo][k] = fminf(A.N[xo][k], valid ? D : INFINITY);
                     } else {
-                        float tt = fmaf(D, -g.c2, A.cref[xo][k]);
+                        float tt = fmaf(D, nc2, A.cref[xo][k]);
                         if (bord)
                             tt = valid ? tt : -INFINITY;
                         const float e = __builtin_amdgcn_exp2f(tt);

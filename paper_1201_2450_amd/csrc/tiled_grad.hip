@@ -183,7 +183,7 @@ __global__ void __launch_bounds__((Lay<SAME, M>::THREADS))
     // z-block), uniform over the wave; both sweeps meet the same barriers
     const bool border = (X0 - 2 - M < 1) || (X0 + kBX + 1 + M > nx) || (Y0 - 2 - M < 1) ||
                         (Y0 + kTY + 1 + M > ny) || (zb - 2 - M < 1) || (zb + kBZ + 1 + M > nz);
-    const float c2 = g.c2;
+    const float nc2 = in_vgpr(-g.c2);  // the exponent's factor, in a vector register
 
     for (int slot = 0; slot < 2; ++slot) {
         const int j = slot == 0 ? (k + 1 == g.np ? 0 : k + 1) : (k == 0 ? g.np - 1 : k - 1);
@@ -333,8 +333,8 @@ __global__ void __launch_bounds__((Lay<SAME, M>::THREADS))
                         for (int xe = 0; xe < kEX; ++xe)
 #pragma unroll
                             for (int ze = 0; ze < kEZ; ++ze) {
-                                const float w1 = __builtin_amdgcn_exp2f(fmaf(D[xe][ze], -c2, L1[xe][ze]));
-                                const float w2 = __builtin_amdgcn_exp2f(fmaf(D[xe][ze], -c2, sl[xe][ze]));
+                                const float w1 = __builtin_amdgcn_exp2f(fmaf(D[xe][ze], nc2, L1[xe][ze]));
+                                const float w2 = __builtin_amdgcn_exp2f(fmaf(D[xe][ze], nc2, sl[xe][ze]));
                                 const float r = SAME ? rc[xe][ze] : fk[xe][ze] - bf[xe * G::ZL + ze];
                                 const float r2 = r * r;
                                 float gv = fmaf(w2, r2 - se[xe][ze], w1 * (r2 - e1[xe][ze]));
@@ -602,7 +602,7 @@ __global__ void __launch_bounds__(THREADS) grad_lds_kernel(Geo g, GradArgs a, fl
     // 0..31 included) has v or v + delta outside the grid
     const bool border = (X0 - 2 - M < 0) || (X0 + TX - 1 + M >= nx) || (Y0 - 3 - M < 0) ||
                         (Y0 + 28 + M >= ny) || (Z0 - 2 - M < 0) || (Z0 + TZ - 1 + M >= nz);
-    const float c2 = g.c2;
+    const float nc2 = in_vgpr(-g.c2);  // the exponent's factor, in a vector register
     constexpr int S = 2 * M + 1;
     const bool want_u = gpad != nullptr;  // uniform: without dE/du only stage 1 runs
 
@@ -722,8 +722,8 @@ __global__ void __launch_bounds__(THREADS) grad_lds_kernel(Geo g, GradArgs a, fl
                         for (int ex = 0; ex < B1X; ++ex)
 #pragma unroll
                             for (int ez = 0; ez < B1Z; ++ez) {
-                                const float w1 = __builtin_amdgcn_exp2f(fmaf(D[ex][ez], -c2, L1[ex][ez]));
-                                const float w2 = __builtin_amdgcn_exp2f(fmaf(D[ex][ez], -c2, sl[ex][ez]));
+                                const float w1 = __builtin_amdgcn_exp2f(fmaf(D[ex][ez], nc2, L1[ex][ez]));
+                                const float w2 = __builtin_amdgcn_exp2f(fmaf(D[ex][ez], nc2, sl[ex][ez]));
                                 const float r = rc[ex][ez];
                                 const float r2 = r * r;
                                 float gv = fmaf(w2, r2 - se[ex][ez], w1 * (r2 - e1[ex][ez]));
