@@ -31,10 +31,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = ("TNLM voxel-updates/s + fwd/adjoint ms, 10×256²×128, "
           "FP32 vs BF16, % VALU peak")
-# MI355X FP32 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2 (packed)
-# x 2.4 GHz
+# MI355X FP32 vector peak: 256 CUs x 4 SIMDs x 64 lanes x 2 (FMA) / 2 cycles
+# x 2.4 GHz; plain (non-packed) FMAs whose operands are all vector registers
+# issue at that rate (one wave64 instruction per SIMD every ~2.1 cycles,
+# measured), FMAs reading a scalar register at half of it
 PEAK_FP32_TFLOPS = 157.3
-PEAK_FP32_NONPACKED_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 # algorithmic flops per Jacobi voxel-update and search offset, patch 3^3:
 # squared difference 2 + separable 3-tap box sums 6 (once per link), then per
 # direction: exponent 2, numerator FMA 2, normaliser add 1 (x2 directions)
@@ -200,9 +201,7 @@ def regulariser(args, w, dev):
     roofline = {"bound": "alu", "achieved": ach, "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": ach / PEAK_FP32_TFLOPS, "traffic": None,
                 "kernel": "tnlm_grad (exact adjoint)",
-                "algorithmic_flop_per_launch": alg,
-                "peak_without_packed_fp32": PEAK_FP32_NONPACKED_TFLOPS,
-                "frac_without_packed_fp32": ach / PEAK_FP32_NONPACKED_TFLOPS}
+                "algorithmic_flop_per_launch": alg}
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle gradient on a sample ...")
@@ -361,8 +360,6 @@ def recon_main(args, dev):
                 "kernel": "tnlm_ct_backproject",
                 "algorithmic_flop_per_launch": flop,
                 "ray_voxel_pairs_per_launch": rays * pairs_per_ray,
-                "peak_without_packed_fp32": PEAK_FP32_NONPACKED_TFLOPS,
-                "frac_without_packed_fp32": ach / PEAK_FP32_NONPACKED_TFLOPS,
                 "projector_achieved": flop / (r["project_ms"] / 1e3) / 1e12,
                 "note": ("each (ray, voxel) pair is one 64-lane gather: the CUs' texture "
                          "addressers, not the FP32 ALUs or HBM, set the time (80-87 % busy "
@@ -482,10 +479,6 @@ def main():
                 "traffic": prof.get("traffic"),
                 "kernel": "tnlm_jacobi_step",
                 "algorithmic_flop_per_launch": alg_flop}
-    # without packed FP32 (disabled in this build) the vector peak is half:
-    # 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz
-    roofline["peak_without_packed_fp32"] = PEAK_FP32_NONPACKED_TFLOPS
-    roofline["frac_without_packed_fp32"] = achieved / PEAK_FP32_NONPACKED_TFLOPS
     if "counter_flop" in prof:
         # the hardware's count of FP32 operations (64 x (ADD + MUL + TRANS +
         # 2 FMA) wave instructions) over the same measured launch time
@@ -493,7 +486,6 @@ def main():
         roofline["counter_achieved"] = c
         roofline["counter_frac"] = c / PEAK_FP32_TFLOPS
         roofline["counter_flop_per_launch"] = prof["counter_flop"]
-        roofline["counter_frac_without_packed_fp32"] = c / PEAK_FP32_NONPACKED_TFLOPS
         roofline["counter_note"] = ("hardware FP32 operation count: includes work the "
                                     "algorithmic count leaves out (each distance once per "
                                     "direction, lane-block halos, reference distances); "
