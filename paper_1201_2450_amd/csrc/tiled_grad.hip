@@ -480,14 +480,14 @@ __global__ void __launch_bounds__(256) fold_kernel(Geo g, const float *gpad, flo
 // position of its tile (stage 1) into an LDS field, and box-sums that field
 // back onto its outputs (stage 2), so every exponential serves the 27
 // outputs around its position:
-//   * tile: TX (x) x 28 (y) x TZ (z) padded outputs of one phase, 16
-//     32-lane segments (512 threads); lane l of every segment sits on grid
-//     row Y0 - 3 + l;
-//   * stage 1: segment s takes a 3 (x) x 4 (z) block of the 6 x 32 Gv
-//     positions (grid x X0-2 .. X0+3, z Z0-2 .. Z0+29): squared differences
+//   * tile: TX = 4 (x) x TY = 28 (y) x TZ = 14 (z) padded outputs of one
+//     phase, 8 32-lane segments (256 threads, so two workgroups share a CU);
+//     lane l of every segment sits on grid row Y0 - 3 + l;
+//   * stage 1: segment s takes a 3 (x) x 4 (z) block of the 6 x 16 Gv
+//     positions (grid x X0-2 .. X0+3, z Z0-2 .. Z0+13): squared differences
 //     on its 5 x 6 block, box sums along z, x (pair sums shared) and y (DPP),
 //     both weights, Gv and the image part; Gv goes to LDS;
-//   * stage 2: segment s < 15 owns 4 (x) x 2 (z) outputs: reads the 6 x 4
+//   * stage 2: segment s < 7 owns 4 (x) x 2 (z) outputs: reads the 6 x 4
 //     Gv block around them, box sums along z, x and y (DPP), multiplies by
 //     Delta = U_k(q') - U_j(q' + delta) and accumulates;
 //   * u_j and the neighbour's statistics are staged per dx as above; per
