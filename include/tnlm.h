@@ -231,7 +231,10 @@ typedef struct tnlm_ct_geom {
 /* Limits: every size >= 1; np*nx*ny*nz and np*na*nu*nv < 2^31; sid, sdd,
  * du, dv finite and > 0; the source and the detector outside the volume:
  * sid and sdd - sid larger than the volume's half-diagonal in the gantry
- * plane (TNLM_EINVAL otherwise). */
+ * plane (TNLM_EINVAL otherwise). The angles sit in device memory and are not
+ * checked: a non-finite angle defines no ray, so every pixel of its
+ * projection is NaN and the transpose adds NaN to every voxel of its phase
+ * (other angles and phases are unaffected). */
 
 /* tnlm_ct_project — proj = P vol for every phase (Eq. (1)). vol and proj
  * must not overlap. */

@@ -98,8 +98,14 @@ __global__ void __launch_bounds__(kBlock) project_kernel(CTG g, const float *vol
     const int64_t rr = t - (int64_t)i * g.R;
     const int a = (int)(rr / ((int64_t)g.nu * g.nv));
     const int iu = (int)((rr / g.nv) % g.nu), iv = (int)(rr % g.nv);
+    const float th = g.angles[(int64_t)i * g.na + a];
+    // a non-finite angle defines no ray: its projection is NaN
+    if (!isfinite(th)) {
+        proj[t] = __builtin_nanf("");
+        return;
+    }
     float S[3], d[3];
-    ray_of(g, g.angles[(int64_t)i * g.na + a], iu, iv, S, d);
+    ray_of(g, th, iu, iv, S, d);
     const int n[3] = {g.nx, g.ny, g.nz};
     float c[3];
     for (int k = 0; k < 3; ++k)
@@ -185,7 +191,7 @@ constexpr int kTabBytes = 32 * 1024;
 
 // max and min of two floats as single instructions: fmaxf/fminf re-quiet
 // (canonicalise) loop-invariant operands on every iteration; the operands
-// here are never NaN
+// here are never NaN (angles are finite by then, the geometry is checked)
 __device__ __forceinline__ float vmaxf(float a, float b)
 {
     float r;
@@ -265,6 +271,13 @@ __global__ void __launch_bounds__(kBlock) backproject_kernel(CTG g, const float 
             c = tab[2 * k + 1];
         } else {
             sincosf(th, &s, &c);
+        }
+        // a non-finite angle (whose sine and cosine are NaN) defines no ray:
+        // it adds NaN, as its projection holds NaN, and its footprint, which
+        // would span the whole detector, is never visited
+        if (!(fabsf(s) <= 1.f)) {
+            acc = __builtin_nanf("");
+            continue;
         }
         // footprint: bounding box of the corners projected onto the detector
         // (pixel units). The detector coordinate u and the magnification m

@@ -93,6 +93,35 @@ def test_projector_and_transpose_match_the_oracle(gm):
     assert abs(lhs - rhs) <= allow
 
 
+
+@pytest.mark.parametrize("gm", [GEOMS[4], GEOMS[3]], ids=["angle-tables", "sincosf"])
+def test_non_finite_angles_give_nan_for_their_rays_and_phase_only(gm):
+    """A NaN or infinite angle defines no ray: its projections are NaN, the
+    transpose puts NaN on every voxel of its phase, and every other ray and
+    phase is bitwise what the same call gives with finite angles (both
+    transpose paths: per-block angle tables and per-thread sincosf)."""
+    nx, ny, nz, nu, nv, na, np_, sid, sdd, du, dv = gm
+    angles = np.random.default_rng(3).uniform(0, 2 * np.pi, size=(np_, na))
+    bad = angles.copy()
+    bad[0, 1], bad[0, na - 1] = np.nan, np.inf
+    geo, og, _, at = setup(nx, ny, nz, nu, nv, na, np_, sid, sdd, du, dv, angles=angles)
+    _, _, _, atb = setup(nx, ny, nz, nu, nv, na, np_, sid, sdd, du, dv, angles=bad)
+    say(f"non-finite angles {gm[:7]}")
+    rng = np.random.default_rng(4)
+    xt = torch.from_numpy(rng.uniform(0.0, 1.0, size=og.vol_shape).astype(np.float32)).to(device())
+    yt = torch.from_numpy(rng.normal(0.0, 1.0, size=og.proj_shape).astype(np.float32)).to(device())
+    p, pb = tnlm.ct.project(xt, geo, at), tnlm.ct.project(xt, geo, atb)
+    b = tnlm.ct.backproject(yt, geo, at, og.vol_shape)
+    bb = tnlm.ct.backproject(yt, geo, atb, og.vol_shape)
+    torch.cuda.synchronize()
+    p, pb, b, bb = host(p), host(pb), host(b), host(bb)
+    assert np.isnan(pb[0, 1]).all() and np.isnan(pb[0, na - 1]).all()
+    keep = np.ones((np_, na), dtype=bool)
+    keep[0, 1] = keep[0, na - 1] = False
+    assert np.isfinite(p).all() and np.array_equal(pb[keep], p[keep])
+    assert np.isnan(bb[0]).all()
+    assert np.isfinite(b).all() and np.array_equal(bb[1:], b[1:])
+
 def test_analytic_phantom_projections_and_empty_rays():
     """The phantom's voxelised projections on the GPU track the analytic
     line integrals of its ellipsoids (discretisation error only, as on the
