@@ -31,9 +31,11 @@ class Geometry:
     dv: float
 
 
-def _g(geo: Geometry, vol_shape, angles: torch.Tensor) -> _lib.CTGeom:
+def _g(geo: Geometry, vol_shape, angles: torch.Tensor, device) -> _lib.CTGeom:
     if angles.dtype != torch.float32 or not angles.is_cuda or not angles.is_contiguous():
         raise ValueError("angles: contiguous float32 GPU tensor (Np, Na)")
+    if angles.device != device:
+        raise ValueError("angles on a different device")
     np_, nx, ny, nz = vol_shape
     if angles.dim() != 2 or angles.shape[0] != np_:
         raise ValueError("angles must be (Np, Na)")
@@ -62,7 +64,7 @@ def _stream(t):
 
 def project(vol, geo: Geometry, angles, out=None):
     """P vol for every phase: (Np, Na, Nu, Nv) float32."""
-    g = _g(geo, vol.shape, angles)
+    g = _g(geo, vol.shape, angles, vol.device)
     shp = proj_shape(geo, vol.shape, angles.shape[1])
     if out is None:
         out = torch.empty(shp, dtype=torch.float32, device=vol.device)
@@ -73,7 +75,7 @@ def project(vol, geo: Geometry, angles, out=None):
 
 def backproject(proj, geo: Geometry, angles, vol_shape, out=None):
     """P^T proj for every phase: (Np, Nx, Ny, Nz) float32."""
-    g = _g(geo, vol_shape, angles)
+    g = _g(geo, vol_shape, angles, proj.device)
     if out is None:
         out = torch.empty(vol_shape, dtype=torch.float32, device=proj.device)
     check(_lib.lib.tnlm_ct_backproject(
@@ -89,7 +91,7 @@ class CGLS:
     layout of include/tnlm.h."""
 
     def __init__(self, y, x, geo: Geometry, angles):
-        self.g = _g(geo, x.shape, angles)
+        self.g = _g(geo, x.shape, angles, x.device)
         self.x, self.geo, self.angles = x, geo, angles
         n = _lib.lib.tnlm_ct_workspace_bytes(ctypes.byref(self.g))
         if n == ctypes.c_size_t(-1).value:
