@@ -270,3 +270,39 @@ def test_recon128_at_full_size_on_sampled_projections():
         assert_within(b[i:i + 1], ref, bnd, f"recon128 P^T y, phase {i} angle {a}")
     others = [k for k in range(w.np_) if k not in dict(picks)]
     assert np.all(b[others] == 0.0)
+
+
+def test_tnlm_r_outer_iteration_replays_bitwise_from_a_hip_graph():
+    """The reconstruction calls allocate, clear and synchronise nothing
+    either (CGLS keeps its scalars on the device), so a whole TNLM-R outer
+    iteration (CGLS initialisation, three CGLS iterations, the Eq. (8) step,
+    positivity) can be captured in a HIP graph: three replays on new
+    projections, with eager runs between them, are each bitwise equal to the
+    same calls run eagerly."""
+    nx, ny, nz, nu, nv, na, np_, sid, sdd, du, dv = GEOMS[1]
+    geo, og, _, at = setup(nx, ny, nz, nu, nv, na, np_, sid, sdd, du, dv, seed=5)
+    say(f"TNLM-R graph capture {GEOMS[1][:7]}")
+    rng = np.random.default_rng(6)
+    new_y = lambda: torch.from_numpy(
+        rng.uniform(0.0, 1.0, size=og.proj_shape).astype(np.float32)).to(device())
+    y = new_y()
+    f0 = torch.from_numpy(rng.uniform(0.0, 0.5, size=og.vol_shape).astype(np.float32)).to(device())
+    kw = dict(mu=0.5, d=1, M=1, h=0.1, outer=1, cg_iters=3)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        tnlm.ct.reconstruct(y, geo, at, f0, **kw)  # warm-up outside the capture
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        f_cap = tnlm.ct.reconstruct(y, geo, at, f0, **kw)
+    for r in range(3):
+        y.copy_(new_y())
+        graph.replay()
+        torch.cuda.synchronize()
+        got = f_cap.clone()
+        ref = tnlm.ct.reconstruct(y, geo, at, f0, **kw)
+        torch.cuda.synchronize()
+        assert torch.isfinite(ref).all()
+        assert torch.equal(got.view(torch.int32), ref.view(torch.int32)), f"replay {r}"
+    del graph
