@@ -131,18 +131,25 @@ def test_exact_gradient(case):
 
 
 def test_results_are_bitwise_deterministic():
-    shape, d, M, h = (3, 16, 12, 40), 1, 2, 0.05
+    """Every entry point twice on the same input: bitwise the same outputs
+    (fixed-order sums, no atomics), on the tiled kernels and, with M = 6, on
+    the generic ones (the full weight tensor too)."""
+    shape, d, h = (3, 16, 12, 40), 1, 0.05
     say(f"determinism {shape}")
     _, u = to_dev(inputs(shape, "phantom", 11))
-    outs = []
-    for _ in range(2):
-        j = tnlm.jacobi_step(u, u, u, 0.5, d=d, M=M, h=h)
-        e, st = tnlm.energy(u, d=d, M=M, h=h, want_stats=True)
-        gt = tnlm.grad(u, d=d, M=M, h=h, mode="exact", stats=st, total=True)
-        torch.cuda.synchronize()
-        outs.append([t.cpu().numpy().copy() for t in (j, e, st, gt)])
-    for a, b in zip(*outs):
-        assert np.array_equal(a.view(np.uint8), b.view(np.uint8))
+    for M in (2, 6):
+        outs = []
+        for _ in range(2):
+            w, lse = tnlm.weights(u, d=d, M=M, h=h, want_w=(M == 6))
+            j = tnlm.jacobi_step(u, u, u, 0.5, d=d, M=M, h=h)
+            e, st = tnlm.energy(u, d=d, M=M, h=h, want_stats=True)
+            g6 = tnlm.grad(u, d=d, M=M, h=h, mode="eq6")
+            gt = tnlm.grad(u, d=d, M=M, h=h, mode="exact", stats=st, total=True)
+            torch.cuda.synchronize()
+            res = [t for t in (w, lse, j, e, st, g6, gt) if t is not None]
+            outs.append([t.cpu().numpy().copy() for t in res])
+        for a, b in zip(*outs):
+            assert np.array_equal(a.view(np.uint8), b.view(np.uint8)), f"M = {M}"
 
 
 @pytest.mark.parametrize("M", [1, 2, 3, 4, 5])
