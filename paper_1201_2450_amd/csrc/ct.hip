@@ -205,6 +205,12 @@ __device__ __forceinline__ float vminf(float a, float b)
     return r;
 }
 
+// four consecutive floats at a 4-byte boundary: one global_load_dwordx4
+// (the HSA targets allow dword-aligned multi-dword loads)
+struct __attribute__((packed, aligned(4))) Float4u {
+    float x, y, z, w;
+};
+
 // start (in floats) of the per-row table, after nang (sin, cos) pairs and
 // aligned for 16-byte reads
 __host__ __device__ inline int row_tab_offset(int nang)
@@ -327,18 +333,46 @@ __global__ void __launch_bounds__(kBlock) backproject_kernel(CTG g, const float 
                 continue;
             const float d01 = d0 * d0 + d1 * d1;
             const float *pcol = pa + (int64_t)iu * g.nv;
+            // length x value of pixel iv's ray inside the voxel; the value is
+            // read only where the ray meets the voxel (add) or handed in (addv)
+            auto addv = [&](bool use, float val, float ov, float z0, float z1) {
+                const float tin = vmaxf(txy0, z0), tout = vminf(txy1, z1);
+                if (use && tout > tin) {
+                    // the hardware square root (within 1 ulp; the argument
+                    // is at least sdd^2, far from denormals)
+                    const float L = __builtin_amdgcn_sqrtf(d01 + ov * ov);
+                    acc = fmaf((tout - tin) * L, val, acc);
+                }
+            };
             auto add = [&](int iv, float ov, float z0, float z1) {
                 const float tin = vmaxf(txy0, z0), tout = vminf(txy1, z1);
                 if (tout > tin) {
-                    // the hardware square root (within 1 ulp; the argument
-                    // is at least sdd^2, far from denormals)
                     const float L = __builtin_amdgcn_sqrtf(d01 + ov * ov);
                     acc = fmaf((tout - tin) * L, pcol[iv], acc);
                 }
             };
             if (TAB) {
                 const float4 *rtab = (const float4 *)(tab + row_tab_offset(nang));
-                for (int iv = v0; iv <= v1c; ++iv) {
+                int iv = v0;
+                if (g.nv >= 4 && v0 <= v1c) {
+                    // the first rows of the column come from one 16-byte load
+                    // (a gather's cost is set by its address count, not its
+                    // width), placed inside the column; rows of it outside
+                    // [v0, v1c] are skipped, so the same rows are summed in
+                    // the same order
+                    const int vs = min(v0, g.nv - 4);
+                    Float4u q;
+                    __builtin_memcpy(&q, pcol + vs, sizeof(q));
+                    const float qv[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const float4 r = rtab[vs + k];
+                        addv(vs + k >= v0 && vs + k <= v1c, qv[k], r.w, fmaf(zlo, r.x, r.y),
+                             fmaf(zlo, r.x, r.z));
+                    }
+                    iv = vs + 4;
+                }
+                for (; iv <= v1c; ++iv) {
                     const float4 r = rtab[iv];
                     add(iv, r.w, fmaf(zlo, r.x, r.y), fmaf(zlo, r.x, r.z));
                 }
