@@ -361,9 +361,11 @@ def recon_main(args, dev):
                 "algorithmic_flop_per_launch": flop,
                 "ray_voxel_pairs_per_launch": rays * pairs_per_ray,
                 "projector_achieved": flop / (r["project_ms"] / 1e3) / 1e12,
-                "note": ("each (ray, voxel) pair is one 64-lane gather: the CUs' texture "
-                         "addressers, not the FP32 ALUs or HBM, set the time (80-87 % busy "
-                         "in the committed counters)")}
+                "note": ("gather-bound, not ALU- or HBM-bound: every (ray, voxel) pair of "
+                         "the projector is one 64-lane gather (texture addressers 87 % busy "
+                         "in the committed counters); the transpose reads four detector rows "
+                         "per gather (49 % busy) and sits between that and its instruction "
+                         "issue")}
         r["ray_voxel_pairs_per_ray"] = pairs_per_ray
     print(json.dumps({"metric": "TNLM-R outer iteration ms (CGLS + Eq. 8 + positivity)",
                       "value": r["tnlm_r_outer_iteration_ms"], "unit": "ms",
