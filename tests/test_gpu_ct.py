@@ -60,6 +60,12 @@ GEOMS = [
     # z = 0 between two voxel layers, and at angle 0 the centre column's in
     # y = 0 (each counted in one layer)
     (8, 6, 4, 9, 7, 5, 2, 30.0, 50.0, 1.5, 1.5),
+    # detector columns of 64 and 128 rows (a wave's rays share one column):
+    # a moderate cone, a steep one (several z crossings per x-y cell) and a
+    # shallow volume that steep rays cross in a few z layers
+    (16, 16, 16, 12, 64, 5, 2, 60.0, 96.0, 1.1, 0.5),
+    (12, 10, 24, 8, 128, 4, 2, 30.0, 50.0, 1.5, 0.9),
+    (8, 8, 6, 8, 64, 3, 1, 30.0, 50.0, 1.5, 1.0),
 ]
 
 
@@ -94,12 +100,14 @@ def test_projector_and_transpose_match_the_oracle(gm):
 
 
 
-@pytest.mark.parametrize("gm", [GEOMS[4], GEOMS[3]], ids=["angle-tables", "sincosf"])
+@pytest.mark.parametrize("gm", [GEOMS[4], GEOMS[3], GEOMS[5]],
+                         ids=["angle-tables", "sincosf", "whole-columns"])
 def test_non_finite_angles_give_nan_for_their_rays_and_phase_only(gm):
     """A NaN or infinite angle defines no ray: its projections are NaN, the
     transpose puts NaN on every voxel of its phase, and every other ray and
     phase is bitwise what the same call gives with finite angles (both
-    transpose paths: per-block angle tables and per-thread sincosf)."""
+    transpose paths: per-block angle tables and per-thread sincosf; waves
+    that hold whole detector columns)."""
     nx, ny, nz, nu, nv, na, np_, sid, sdd, du, dv = gm
     angles = np.random.default_rng(3).uniform(0, 2 * np.pi, size=(np_, na))
     bad = angles.copy()
