@@ -23,8 +23,12 @@
 //     y/z halo of the window, clamped to the grid (clamp-to-edge); a lane
 //     clamps a (row, z) cell once and copies it from every plane; the LDS
 //     layout is [row][plane][z] with an odd row stride, so one base address
-//     per lane serves every plane of a search offset through the 8-bit
-//     offsets of ds_read2, and lanes (rows) never share a bank;
+//     per lane and dy serves every plane and dz through the 8-bit offsets of
+//     ds_read2, and lanes (rows) never share a bank;
+//   * the offsets of one (dx, dy) are taken with dz innermost and unrolled:
+//     the lane's window of u_j and f_j moves by one z slot per dz, so it
+//     stays in registers and only the new slot of every plane is read from
+//     LDS (8 instead of 26 LDS reads per offset at M = 3);
 //   * with HALVES = 2 two sets of waves own the same outputs and split the
 //     (dy, dz) offset pairs of every dx (alternate pairs), sharing the staged
 //     tile; their sums are added in a fixed order;
@@ -71,9 +75,9 @@ struct TG {
     static constexpr int FPL = C::BX;             // f_j planes per dx
     static constexpr int RU = (UPL * ZL) | 1;     // odd row strides: rows never
     static constexpr int RF = (FPL * ZL) | 1;     // share an LDS bank
-    // offsets from a lane's per-(dy, dz) base: plane xp at xp*ZL, z-slot k
-    static_assert((UPL - 1) * ZL + kBZ + 1 < 256,
-                  "one ds_read2 base per lane must reach every plane");
+    // offsets from a lane's per-dy base: plane xp at xp*ZL, z-slot k + M + dz
+    static_assert((UPL - 1) * ZL + kBZ + 1 + 2 * M < 256,
+                  "one ds_read2 base per (lane, dy) must reach every plane and dz");
 };
 
 struct TileGrid {
@@ -153,8 +157,16 @@ __device__ __forceinline__ void box_dist(const float (&ui)[BX + 2][kBZ + 2], Loa
     }
 }
 
+// Least waves per SIMD the compiler must allow: two where the unrolled
+// window would otherwise spill into a third register file and leave one wave
+// per SIMD (M = 1 with f_j); elsewhere its own choice, which schedules the
+// loop better than a forced bound.
+template <int M, int MODE>
+constexpr int kMinWaves = (M == 1 && MODE != FWD_WEIGHTS && MODE != FWD_ENERGY) ? 2 : 1;
+
 template <typename T, int M, int MODE, class C>
-__global__ void __launch_bounds__(C::THREADS) fwd_tiled_kernel(Geo g, FwdArgs a, TileGrid tg)
+__global__ void __launch_bounds__(C::THREADS) __attribute__((amdgpu_waves_per_eu(kMinWaves<M, MODE>)))
+fwd_tiled_kernel(Geo g, FwdArgs a, TileGrid tg)
 {
     using G = TG<M, C>;
     constexpr int BX = C::BX;
@@ -288,10 +300,69 @@ __global__ void __launch_bounds__(C::THREADS) fwd_tiled_kernel(Geo g, FwdArgs a,
     auto sweep = [&](int j, auto pass_c, auto bord_c, int p0, int pstep) {
         constexpr int pass = decltype(pass_c)::value;
         constexpr bool bord = decltype(bord_c)::value;
+        // one candidate of output (xo, k): its distance D, whether it lies in
+        // the grid, and the neighbour's value fj at it
+        auto take = [&](int xo, int k, float D, bool valid, float fj) {
+            if (pass == PASS_MIN) {
+                A.N[xo][k] = fminf(A.N[xo][k], valid ? D : INFINITY);
+            } else {
+                float tt = fmaf(D, nc2, A.cref[xo][k]);
+                if (bord)
+                    tt = valid ? tt : -INFINITY;
+                const float e = __builtin_amdgcn_exp2f(tt);
+                A.Z[xo][k] += e;
+                if (MODE == FWD_JACOBI || MODE == FWD_EQ6) {
+                    A.N[xo][k] = fmaf(e, fj, A.N[xo][k]);
+                } else if (MODE == FWD_ENERGY) {
+                    const float r = fi[xo][k] - fj;
+                    A.N[xo][k] = fmaf(e * r, r, A.N[xo][k]);
+                }
+            }
+        };
         for (int dx = -M; dx <= M; ++dx) {
             __syncthreads();
             stage(j, dx);
             __syncthreads();
+            if (C::HALVES == 1 && MODE != FWD_WEIGHTS) {
+                // dz innermost and unrolled: the lane's window of u_j (and
+                // f_j) moves by one z slot per dz, so it stays in registers
+                // and only the new slot of every plane is read from LDS
+                for (int dy = -M; dy <= M; ++dy) {
+                    const bool yval = (unsigned)(y + dy) < (unsigned)ny;
+                    lds_float *bu = lds_base(sU + (ry + dy) * G::RU + zoffU - M);
+                    lds_float *bf = lds_base(sF + (ry + dy) * G::RF + zoffF - M);
+                    float uw[G::UPL][kBZ + 2 + 2 * M];
+                    float fw[MODE == FWD_WEIGHTS ? 1 : G::FPL][kBZ + 2 * M];
+#pragma unroll
+                    for (int q = 0; q < S; ++q) {
+                        const int dz = q - M;
+#pragma unroll
+                        for (int xp = 0; xp < G::UPL; ++xp)
+#pragma unroll
+                            for (int k = (q == 0 ? 0 : kBZ + 1); k < kBZ + 2; ++k)
+                                uw[xp][q + k] = bu[xp * G::ZL + q + k];
+                        if (MODE != FWD_WEIGHTS && pass != PASS_MIN) {
+#pragma unroll
+                            for (int xo = 0; xo < G::FPL; ++xo)
+#pragma unroll
+                                for (int k = (q == 0 ? 0 : kBZ - 1); k < kBZ; ++k)
+                                    fw[xo][q + k] = bf[xo * G::ZL + q + k];
+                        }
+                        auto uj = [&](int xp, int k) { return uw[xp][q + k]; };
+                        auto out = [&](int xo, int k, float D) {
+                            bool valid = true;
+                            if (bord)
+                                valid = yval & ((unsigned)(x0 + xo + dx) < (unsigned)nx) &
+                                        ((unsigned)(zb + k + dz) < (unsigned)nz);
+                            take(xo, k, D, valid,
+                                 MODE == FWD_WEIGHTS || pass == PASS_MIN ? 0.f
+                                                                         : fw[xo][q + k]);
+                        };
+                        box_dist<BX>(ui, uj, out);
+                    }
+                }
+                continue;
+            }
             for (int pr = p0; pr < S * S; pr += pstep) {
                 const int dy = pr / S - M, dz = pr - (pr / S) * S - M;
                 const bool yval = (unsigned)(y + dy) < (unsigned)ny;
@@ -303,21 +374,8 @@ __global__ void __launch_bounds__(C::THREADS) fwd_tiled_kernel(Geo g, FwdArgs a,
                     if (bord)
                         valid = yval & ((unsigned)(x0 + xo + dx) < (unsigned)nx) &
                                 ((unsigned)(zb + k + dz) < (unsigned)nz);
-                    if (pass == PASS_MIN) {
-                        A.N[xo][k] = fminf(A.N[xo][k], valid ? D : INFINITY);
-                    } else {
-                        float tt = fmaf(D, nc2, A.cref[xo][k]);
-                        if (bord)
-                            tt = valid ? tt : -INFINITY;
-                        const float e = __builtin_amdgcn_exp2f(tt);
-                        A.Z[xo][k] += e;
-                        if (MODE == FWD_JACOBI || MODE == FWD_EQ6) {
-                            A.N[xo][k] = fmaf(e, bf[xo * G::ZL + k], A.N[xo][k]);
-                        } else if (MODE == FWD_ENERGY) {
-                            const float r = fi[xo][k] - bf[xo * G::ZL + k];
-                            A.N[xo][k] = fmaf(e * r, r, A.N[xo][k]);
-                        }
-                    }
+                    take(xo, k, D, valid,
+                         MODE == FWD_WEIGHTS || pass == PASS_MIN ? 0.f : bf[xo * G::ZL + k]);
                 };
                 box_dist<BX>(ui, uj, out);
             }
